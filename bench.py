@@ -1,0 +1,164 @@
+#!/usr/bin/env python
+"""Throughput of the improved 3D colour-gradient LB step on one MI355X.
+
+Workload: the Galilean droplet, a 128^3 periodic D3Q19 lattice, density and
+viscosity ratio 1, droplet radius 20 at a seeded random centre, uniform
+initial velocity (0.05, 0.05, 0.05), tau_v drawn in [0.6, 1.0] from the seed,
+plain FP32 populations.  A step is one full time step of the method (moments,
+colour gradient, MRT collision with correction term and perturbation,
+recoloring, streaming).  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + HBM GB/s (% peak): FP32 plain vs FP16-store/surrogate at stated error"
+HBM_PEAK_GBPS = 8000.0
+# Algorithmic HBM bytes per node of one launch of the collision pass: read 38
+# populations, read the node's aux value (rho^N, Qbar), write 38 populations.
+# Shifted 16-bit storage adds the writers' (rho_R, rho_B) read and the node's
+# own (rho_R, rho_B) write.
+COLLIDE_BYTES = {"fp32": 38 * 4 + 16 + 38 * 4, "fp16s": 38 * 2 + 16 + 8 + 38 * 2 + 8,
+                 "bf16s": 38 * 2 + 16 + 8 + 38 * 2 + 8}
+# The method's own minimum per node and step: 38 populations read + written.
+STEP_BYTES = {"fp32": 304, "fp16s": 152, "bf16s": 152}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "d3q19.hpp"):
+        with open(os.path.join(ROOT, "paper_1904_03618_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage):
+    """HBM bytes per collision launch from the committed rocprofv3 counter
+    summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_collide_{storage}_galilean128_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_form(B, cases, storage, steps, warmup, timing=True):
+    import torch
+    s = B.Solver(cases, storage=storage)
+    try:
+        s.step(warmup)
+        torch.cuda.synchronize()
+        if timing:
+            B.lbcg_timing(s.h, 1)
+            B.lbcg_timing_read(s.h)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kt = B.lbcg_timing_read(s.h) if timing else None
+        fl = s.fields(0)
+        return ms, kt, {k: v.double() for k, v in fl.items() if k != "diag"}
+    finally:
+        s.close()
+
+
+def cpu_baseline(p, fl, budget_s):
+    """The FP64 oracle on the host cores, on a bounded sample of the same
+    workload (the full 128^3 lattice for a few steps)."""
+    from oracle import oracle as O
+    f = O.init(p, fl["rhoR"], fl["rhoB"], fl["ux"], fl["uy"], fl["uz"])
+    N = p["nx"] * p["ny"] * p["nz"]
+    t = time.time()
+    O.run(p, f, 1)
+    dt1 = time.time() - t
+    n = max(1, min(50, int(budget_s / max(dt1, 1e-3)) - 1))
+    t = time.time()
+    O.run(p, f, n)
+    dt = time.time() - t
+    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "sample": f"galilean droplet 128^3, FP64 oracle, {n} timed steps after 1 untimed "
+                      f"({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--forms", default="fp16s,bf16s", help="extra storage forms to time ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the step runs on a single MI355X; "
+              "multi-GPU slab decomposition is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1904_03618_amd import lbcg as B
+    from paper_1904_03618_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    p, fl = W.galilean_droplet(128, 20.0, seed=1904)
+    N = p["nx"] * p["ny"] * p["nz"]
+    cases = [(p, fl)]
+
+    ms, kt, ref = run_form(B, cases, "fp32", args.steps, args.warmup)
+    ms_step = ms / args.steps
+    mlups = N * args.steps / (ms * 1e-3) / 1e6
+    col_ms, col_n = kt["collide"]
+    aux_ms, aux_n = kt["aux"]
+    avg_col = col_ms / col_n
+    ach = COLLIDE_BYTES["fp32"] * N / (avg_col * 1e-3) / 1e9
+    traffic = measured_traffic("fp32")
+
+    forms = {}
+    for st in [s for s in args.forms.split(",") if s]:
+        fms, fkt, ff = run_form(B, cases, st, args.steps, args.warmup)
+        c_ms, c_n = fkt["collide"]
+        err_n = float((ff["rhoN"] - ref["rhoN"]).abs().max())
+        err_u = float(max((ff[k] - ref[k]).abs().max() for k in ("ux", "uy", "uz")))
+        forms[st] = {"MLUPS": N * args.steps / (fms * 1e-3) / 1e6, "ms_per_step": fms / args.steps,
+                     "collide_avg_ms": c_ms / c_n,
+                     "collide_GBps": COLLIDE_BYTES[st] * N / (c_ms / c_n * 1e-3) / 1e9,
+                     "max_abs_diff_vs_fp32_after_steps": {"rhoN": err_n, "u": err_u,
+                                                          "steps": args.steps + args.warmup}}
+
+    out = {
+        "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "galilean droplet 128^3 (periodic, R=20, u0=0.05, seed 1904)",
+                   "lattice": [128, 128, 128], "storage": "fp32", "tau_v": p["tau_v"][0],
+                   "parallelism": "single GPU"},
+        "step_algorithmic_GBps": mlups * 1e6 * STEP_BYTES["fp32"] / 1e9,
+        "kernels_avg_ms": {"aux": aux_ms / aux_n, "collide": avg_col},
+        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBPS, "kernel": "k_collide<fp32>",
+                     "bytes_per_node": COLLIDE_BYTES["fp32"],
+                     "traffic": traffic},
+        "forms": forms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, fl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * lbcg.h -- C ABI of the MI355X (gfx950) implementation of the improved
+ * three-dimensional colour-gradient lattice Boltzmann model of Wen, Li, Yu &
+ * Luo (arXiv 1904.03618): two immiscible fluids, red (k = 0) and blue (k = 1),
+ * each carried by a D3Q19 distribution (Eq. 1, 5), advanced by the MRT
+ * collision with the improved equilibrium and the error-cancelling correction
+ * term (Eq. 18, 40-49), the tau-independent perturbation (Eq. 8, 53), the
+ * Latva-Kokko recoloring (Eq. 10-12) and streaming (text after Eq. 12) with
+ * periodic, halfway bounce-back and wetting walls.
+ *
+ * Conventions shared by every call:
+ *   - node order is x-fastest: node = x + nx*(y + ny*z);
+ *   - every GPU operation is enqueued on the HIP stream given to lbcg_init
+ *     (NULL = the legacy default stream); calls are asynchronous except
+ *     lbcg_moments (which returns FP64 sums to the host) and the periodic
+ *     stability check inside lbcg_step;
+ *   - one handle must not be used from two host threads at once;
+ *   - every call returns LBCG_OK (0) or a negative error code; the text of the
+ *     last error of the calling thread is available from lbcg_last_error().
+ */
+#ifndef LBCG_H
+#define LBCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBCG_OK 0
+#define LBCG_EINVAL (-1)     /* invalid argument (sizes, parameters, pointers) */
+#define LBCG_ENOMEM (-2)     /* device allocation failed */
+#define LBCG_EDEVICE (-3)    /* a HIP call failed */
+#define LBCG_EUNSTABLE (-4)  /* NaN/Inf or negative colour density detected */
+#define LBCG_ESTATE (-5)     /* NULL, freed or otherwise unusable handle */
+
+#define LBCG_PERIODIC 0
+#define LBCG_WALL 1          /* halfway bounce-back wall half a link beyond the
+                                first and last node of the axis */
+
+/* Population storage formats.  Arithmetic is always FP32. */
+#define LBCG_FP32 0          /* plain FP32 populations (152 B per node) */
+#define LBCG_FP16S 1         /* FP16 deviations from the local rest state
+                                rho_k phi_i^k, scaled by 2^10 (76 B per node) */
+#define LBCG_BF16S 2         /* BF16 deviations from rho_k phi_i^k (76 B per node) */
+
+/*
+ * One independent simulation box.  Fluid parameters follow the paper:
+ *   rho_in    rho_R^in, rho_B^in, the reference densities of the phase field
+ *             rho^N (text after Eq. 8); must satisfy the pressure balance
+ *             rho_R^in (1 - alpha_R) = rho_B^in (1 - alpha_B) (Sec. IV.A)
+ *             to 1e-12 relative;
+ *   alpha     alpha_R, alpha_B of the pressure weights phi_i^k (Eq. 13), in [0, 1);
+ *   tau_v     bulk shear relaxation times tau_v^R, tau_v^B (Eq. 52), > 1/2;
+ *   A         surface-tension parameters A_R, A_B (Eq. 8); with the Eq. (53)
+ *             form sigma = 2 (A_R + A_B) / 9;
+ *   beta      recoloring parameter (Eq. 10-11);
+ *   delta     half-width of the tau_v interpolation (Eq. 52, 0.98 usual);
+ *   tau_e, tau_q, tau_pi   remaining relaxation times of S (Eq. 44), > 1/2;
+ *   force     uniform body-force density (lattice units);
+ *   grav, rho_ref          buoyancy: the force density at a node is
+ *             force + (rho - rho_ref) * grav;
+ *   bc        per axis LBCG_PERIODIC or LBCG_WALL; at most one axis may be a wall;
+ *   theta_deg contact angle, measured through the red fluid, of the low and
+ *             high wall of the wall axis (90 = neutral);
+ *   improved  1: improved model (Eq. 18 equilibrium + correction term Eq. 45);
+ *             0: the same MRT model without both improvements.
+ */
+typedef struct lbcg_case {
+    int32_t nx, ny, nz;
+    int32_t bc[3];
+    double theta_deg[2];
+    double rho_in[2];
+    double alpha[2];
+    double tau_v[2];
+    double A[2];
+    double beta, delta;
+    double tau_e, tau_q, tau_pi;
+    double force[3];
+    double grav[3];
+    double rho_ref;
+    int32_t improved;
+    int32_t reserved;
+} lbcg_case;
+
+/* Initial fields of one case: FP64 arrays of nx*ny*nz values, x-fastest.
+ * on_device = 0: host memory; 1: device memory.  Read once during lbcg_init;
+ * the caller keeps ownership. */
+typedef struct lbcg_fields {
+    const double *rhoR, *rhoB, *ux, *uy, *uz;
+    int32_t on_device;
+    int32_t reserved;
+} lbcg_fields;
+
+/* Handle-wide options.  storage: LBCG_FP32 / LBCG_FP16S / LBCG_BF16S.
+ * diag_every: run the stability check every this many steps inside
+ * lbcg_step (0 = never).  block_nodes: nodes per work tile and workgroup
+ * (0 = default 256; 64, 128, 192 or 256).  persistent_blocks: 0 = one
+ * workgroup per tile, >0 = that many workgroups looping over all tiles of all
+ * cases (batched persistent launch). */
+typedef struct lbcg_options {
+    int32_t storage;
+    int32_t diag_every;
+    int32_t block_nodes;
+    int32_t persistent_blocks;
+} lbcg_options;
+
+typedef struct lbcg_handle lbcg_handle;
+
+/*
+ * Create a handle for n_cases independent boxes and set every case to the
+ * equilibrium f^k = f^{k,eq}(rho_k, u0) of the improved (Eq. 18) or original
+ * (Eq. 6) equilibrium at time level 0.  hip_stream is a hipStream_t (may be
+ * NULL).  On success *out receives the handle, which owns all device memory
+ * it allocates.  Errors: LBCG_EINVAL (n_cases < 1, any dimension < 1, more
+ * than one wall axis, alpha outside [0,1), a relaxation time <= 1/2,
+ * rho_in <= 0, broken pressure balance, NULL pointer), LBCG_ENOMEM,
+ * LBCG_EDEVICE.
+ */
+int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init,
+              const lbcg_options *opt, void *hip_stream, lbcg_handle **out);
+
+/*
+ * Advance every case by nsteps time steps.  One step: moments (Eq. 4), phase
+ * field and colour gradient (Eq. 8, 49), correction gradients (Eq. 46-49),
+ * tau_v (Eq. 52), MRT collision with correction, force and perturbation in
+ * moment space (Eq. 41-45, 53), recoloring (Eq. 10-11), pull streaming with
+ * periodic wrap or halfway bounce-back.  Errors: LBCG_ESTATE, LBCG_EINVAL
+ * (nsteps < 0), LBCG_EDEVICE, LBCG_EUNSTABLE (the stability check found a
+ * NaN/Inf or a colour density below -1e-3 rho_in; lbcg_steps_done() then
+ * tells the level that failed).
+ */
+int lbcg_step(lbcg_handle *h, int64_t nsteps);
+
+/*
+ * Macroscopic fields of case case_id at the current level (post-streaming,
+ * before collision): rho_R, rho_B, the phase field rho^N and the mixture
+ * velocity u = (sum_ik e_i f_i^k + F/2)/rho.  Each field pointer is caller-owned
+ * DEVICE memory of nx*ny*nz FP32 values, or NULL to skip it.  diag, if not
+ * NULL, is caller-owned HOST memory for 5 FP64 sums over the case:
+ * {sum rho_R, sum rho_B, sum rho u_x, sum rho u_y, sum rho u_z}; the call then
+ * synchronises the stream.  Errors: LBCG_ESTATE, LBCG_EINVAL (bad case_id),
+ * LBCG_EDEVICE.
+ */
+int lbcg_moments(lbcg_handle *h, int32_t case_id, float *rhoR, float *rhoB, float *rhoN,
+                 float *ux, float *uy, float *uz, double *diag);
+
+/* Release every device resource of the handle.  LBCG_ESTATE for NULL. */
+int lbcg_free(lbcg_handle *h);
+
+/* ---- inspection helpers (tests, checkpoints) ---- */
+
+/* Text of the calling thread's last error ("" if none). */
+const char *lbcg_last_error(void);
+
+/* Number of time steps the handle has completed. */
+int64_t lbcg_steps_done(const lbcg_handle *h);
+
+/* The streaming map the step kernels use: for every direction i and node,
+ * src_node[i*N + node] and src_dir[i*N + node] name the post-collision value
+ * that the pull at (node, i) reads.  Both are caller-owned DEVICE buffers of
+ * 19*N entries.  Errors: LBCG_ESTATE, LBCG_EINVAL, LBCG_EDEVICE. */
+int lbcg_index_map(lbcg_handle *h, int32_t case_id, int64_t *src_node, int8_t *src_dir);
+
+/* Decoded FP32 populations of case case_id at the current level into
+ * caller-owned DEVICE memory f[(k*19 + i)*N + node].  Errors as above. */
+int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f);
+
+/* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
+ * recording an event pair around every kernel of every following step
+ * (enable = 0 stops).  lbcg_timing_read synchronises the stream and writes,
+ * for the kernels {moments/aux pass, wall ghost layer, collision pass}, the
+ * summed duration in milliseconds into ms[3] and the number of recorded
+ * launches into launches[3]; it then clears the totals.  Errors: LBCG_ESTATE,
+ * LBCG_EINVAL (NULL output), LBCG_EDEVICE. */
+int lbcg_timing(lbcg_handle *h, int32_t enable);
+int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches);
+
+/* Number of nodes and storage bytes per population value of the handle. */
+int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id);
+int32_t lbcg_storage_bytes(const lbcg_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBCG_H */

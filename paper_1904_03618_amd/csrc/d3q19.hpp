@@ -1,0 +1,92 @@
+// d3q19.hpp -- lattice constants, storage codecs and per-case parameters of the
+// gfx950 implementation of the improved 3D colour-gradient LB model
+// (Wen, Li, Yu & Luo, arXiv 1904.03618).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbcg.h"
+
+namespace lbcg {
+
+constexpr int Q = 19;
+
+// Eq. (5): D3Q19 velocities, i = 0..18.  Every use sits in a fully unrolled
+// loop, so these fold to immediates.
+__host__ __device__ constexpr int ex(int i)
+{
+    return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int ey(int i)
+{
+    return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int ez(int i)
+{
+    return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+// velocity class: 0 rest, 1 axis (|e|^2 = 1), 2 face diagonal (|e|^2 = 2)
+__host__ __device__ constexpr int ecls(int i) { return i == 0 ? 0 : (i <= 6 ? 1 : 2); }
+// the direction with e_opp = -e_i (pairs (1,2), (3,4), ... (17,18))
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 == 1 ? i + 1 : i - 1); }
+
+// Population storage.  Shifted formats keep d = (f - rho_k phi_i^k) * scale,
+// rho_k being the density of the node that wrote the value.
+template <int ST> struct Storage;
+template <> struct Storage<LBCG_FP32> {
+    using T = float;
+    static constexpr bool shifted = false;
+    __device__ static float dec(T v, float, float) { return v; }
+    __device__ static T enc(float f, float, float) { return f; }
+};
+template <> struct Storage<LBCG_FP16S> {
+    using T = _Float16;
+    static constexpr bool shifted = true;
+    __device__ static float dec(T v, float shift, float inv_scale) { return __builtin_fmaf((float)v, inv_scale, shift); }
+    __device__ static T enc(float f, float shift, float scale) { return (T)((f - shift) * scale); }
+};
+template <> struct Storage<LBCG_BF16S> {
+    using T = __bf16;
+    static constexpr bool shifted = true;
+    __device__ static float dec(T v, float shift, float inv_scale) { return __builtin_fmaf((float)v, inv_scale, shift); }
+    __device__ static T enc(float f, float shift, float scale) { return (T)((f - shift) * scale); }
+};
+
+// Per-case constants, derived on the host in FP64 and rounded once to FP32.
+struct DevCase {
+    int nx, ny, nz, wall;        // wall: -1 none, else the wall axis
+    int N, plane;                // nodes; nodes of one wall plane
+    int improved, pad0;
+    int64_t pop_off;             // first population element of the case
+    int64_t node_off;            // first node of the case in per-node arrays
+    int64_t ghost_off;           // first ghost entry (2 planes) of the case
+    float rin_inv[2];            // 1 / rho_k^in
+    float cs2[2];                // (c_s^k)^2 = (1 - alpha_k)/2
+    float qc[2];                 // 1 - 3 (c_s^k)^2
+    float phi[2][3];             // phi^k for rest / axis / diagonal (Eq. 13)
+    float tauR, tauB, s1, s2, s3, t2, t3, delta;   // Eq. (52) and its parabolas
+    float s_e, s_q, s_pi;        // 1/tau_e, 1/tau_q, 1/tau_pi (Eq. 44)
+    float Asum, beta;            // A_R + A_B; recoloring beta
+    float F[3], g[3], rho_ref;   // force density = F + (rho - rho_ref) g
+    float cot[2];                // cot(theta) of the low / high wall
+    float neg_tol[2];            // stability check: rho_k < neg_tol[k] is unstable
+};
+
+struct StepArgs {
+    const void *fin;             // populations at level t
+    void *fout;                  // populations at level t+1
+    float4 *aux;                 // per node: rho^N, Qbar_x, Qbar_y, Qbar_z (level t)
+    float4 *ghost;               // per wall-plane node: same fields one layer beyond the wall
+    const float2 *rho_prev;      // shifted storage: rho_R, rho_B of the writers of fin
+    float2 *rho_cur;             // shifted storage: rho_R, rho_B written with fout
+    const DevCase *cases;
+    const int2 *tiles;           // (case, first node) per tile
+    int ntiles;
+    float scale, inv_scale;
+};
+
+}  // namespace lbcg

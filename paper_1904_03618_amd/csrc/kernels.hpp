@@ -1,0 +1,584 @@
+// kernels.hpp -- gfx950 kernels of one time step of the improved 3D
+// colour-gradient MRT lattice Boltzmann model (Wen, Li, Yu & Luo).
+//
+// One step at level t is three launches over all tiles of all cases:
+//   k_aux     pull the 38 populations, moments (Eq. 4), phase field rho^N
+//             (text after Eq. 8) and Qbar = u sum_k rho_k (1 - 3 c_s^k^2)
+//             (Eq. 46-49) -> aux
+//   k_ghost   ghost layer one node beyond each wall (wetting rule for rho^N,
+//             odd reflection for Qbar)
+//   k_collide pull the 38 populations again, colour gradient and Q_alpha from
+//             the aux stencil (Eq. 49), tau_v (Eq. 52), the two-colour MRT
+//             collision in moment space (Eq. 41-45, 53 and the body force),
+//             recoloring (Eq. 10-11) and store at the node's own slots: the
+//             next step's pull completes the streaming.
+// The colour gradient at level t needs the level-t densities of all 18
+// neighbours, so the moments pass must finish before the collision pass.
+#pragma once
+
+#include "d3q19.hpp"
+
+namespace lbcg {
+
+// Tile loop with an XCD-aware assignment: workgroups are dealt round-robin to
+// the 8 XCDs, so the tiles are cut into 8 contiguous chunks and XCD j works
+// through chunk j.  Neighbouring tiles (the +-y and +-z stencil partners) then
+// share one L2.
+struct TileRange { int first, stride, end; };
+
+__device__ inline TileRange tile_range(int ntiles)
+{
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G < 8) return {b, G, ntiles};
+    const int j = b & 7, m = b >> 3;
+    const int nb = G / 8 + (j < G % 8 ? 1 : 0);
+    const int t0 = j * (ntiles / 8) + min(j, ntiles % 8);
+    const int t1 = t0 + ntiles / 8 + (j < ntiles % 8 ? 1 : 0);
+    return {t0 + m, nb, t1};
+}
+
+struct Coord {
+    int x, y, z, node;
+    int cx[3], cy[3], cz[3];     // wrapped coordinate - 1, 0, + 1 along each axis
+    bool lo[3], hi[3];           // first / last layer of the wall axis
+};
+
+__device__ inline Coord make_coord(const DevCase &C, int node)
+{
+    Coord c;
+    c.node = node;
+    const int nxy = C.nx * C.ny;
+    c.z = node / nxy;
+    const int r = node - c.z * nxy;
+    c.y = r / C.nx;
+    c.x = r - c.y * C.nx;
+    c.cx[0] = c.x == 0 ? C.nx - 1 : c.x - 1; c.cx[1] = c.x; c.cx[2] = c.x == C.nx - 1 ? 0 : c.x + 1;
+    c.cy[0] = c.y == 0 ? C.ny - 1 : c.y - 1; c.cy[1] = c.y; c.cy[2] = c.y == C.ny - 1 ? 0 : c.y + 1;
+    c.cz[0] = c.z == 0 ? C.nz - 1 : c.z - 1; c.cz[1] = c.z; c.cz[2] = c.z == C.nz - 1 ? 0 : c.z + 1;
+    c.lo[0] = C.wall == 0 && c.x == 0; c.hi[0] = C.wall == 0 && c.x == C.nx - 1;
+    c.lo[1] = C.wall == 1 && c.y == 0; c.hi[1] = C.wall == 1 && c.y == C.ny - 1;
+    c.lo[2] = C.wall == 2 && c.z == 0; c.hi[2] = C.wall == 2 && c.z == C.nz - 1;
+    return c;
+}
+
+// Pull source of direction i: the post-collision value at x - e_i, or, when
+// x - e_i lies beyond a wall (halfway bounce-back), the opposite direction at
+// x itself.
+template <int I>
+__device__ inline void pull_source(const DevCase &C, const Coord &c, int &src, int &dir)
+{
+    constexpr int X = ex(I), Y = ey(I), Z = ez(I);
+    const bool bb = (X == 1 && c.lo[0]) || (X == -1 && c.hi[0]) || (Y == 1 && c.lo[1]) ||
+                    (Y == -1 && c.hi[1]) || (Z == 1 && c.lo[2]) || (Z == -1 && c.hi[2]);
+    const int s = c.cx[1 - X] + C.nx * (c.cy[1 - Y] + C.ny * c.cz[1 - Z]);
+    src = bb ? c.node : s;
+    dir = bb ? opp(I) : I;
+}
+
+struct NodeState {
+    float f[Q];                  // f_i = f_i^R + f_i^B after streaming
+    float rR, rB, jx, jy, jz;
+};
+
+template <int ST, int I>
+__device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    int src, dir;
+    pull_source<I>(C, c, src, dir);
+    const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+    const size_t N = (size_t)C.N;
+    const T vR = base[(size_t)dir * N + src];
+    const T vB = base[(size_t)(Q + dir) * N + src];
+    float shR = 0.f, shB = 0.f;
+    if constexpr (S::shifted) {
+        const float2 rp = a.rho_prev[C.node_off + src];
+        shR = rp.x * C.phi[0][ecls(I)];
+        shB = rp.y * C.phi[1][ecls(I)];
+    }
+    const float fR = S::dec(vR, shR, a.inv_scale);
+    const float fB = S::dec(vB, shB, a.inv_scale);
+    const float ft = fR + fB;
+    s.f[I] = ft;
+    s.rR += fR;
+    s.rB += fB;
+    if constexpr (ex(I) == 1) s.jx += ft;
+    if constexpr (ex(I) == -1) s.jx -= ft;
+    if constexpr (ey(I) == 1) s.jy += ft;
+    if constexpr (ey(I) == -1) s.jy -= ft;
+    if constexpr (ez(I) == 1) s.jz += ft;
+    if constexpr (ez(I) == -1) s.jz -= ft;
+}
+
+template <int ST, int I = 0>
+__device__ inline void pull_all(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
+{
+    if constexpr (I < Q) {
+        pull_one<ST, I>(a, C, c, s);
+        pull_all<ST, I + 1>(a, C, c, s);
+    }
+}
+
+template <int ST>
+__device__ inline void pull_node(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
+{
+    s.rR = s.rB = s.jx = s.jy = s.jz = 0.f;
+    pull_all<ST>(a, C, c, s);
+}
+
+// Force density (reading: uniform part plus buoyancy) and u = (j + F/2)/rho.
+struct Macro { float rho, inv_rho, Fx, Fy, Fz, ux, uy, uz; };
+
+__device__ inline Macro macro(const DevCase &C, const NodeState &s)
+{
+    Macro m;
+    m.rho = s.rR + s.rB;
+    m.inv_rho = 1.0f / m.rho;
+    const float dr = m.rho - C.rho_ref;
+    m.Fx = C.F[0] + dr * C.g[0];
+    m.Fy = C.F[1] + dr * C.g[1];
+    m.Fz = C.F[2] + dr * C.g[2];
+    m.ux = (s.jx + 0.5f * m.Fx) * m.inv_rho;
+    m.uy = (s.jy + 0.5f * m.Fy) * m.inv_rho;
+    m.uz = (s.jz + 0.5f * m.Fz) * m.inv_rho;
+    return m;
+}
+
+__device__ inline float phase_field(const DevCase &C, float rR, float rB)
+{
+    const float a = rR * C.rin_inv[0], b = rB * C.rin_inv[1];
+    return (a - b) / (a + b);
+}
+
+// ----------------------------------------------------------------- k_aux
+template <int ST>
+__global__ __launch_bounds__(256) void k_aux(StepArgs a)
+{
+    const TileRange tr = tile_range(a.ntiles);
+    for (int t = tr.first; t < tr.end; t += tr.stride) {
+        const int2 tl = a.tiles[t];
+        const DevCase &C = a.cases[tl.x];
+        const int node = tl.y + (int)threadIdx.x;
+        if (node >= C.N) continue;
+        const Coord c = make_coord(C, node);
+        NodeState s;
+        pull_node<ST>(a, C, c, s);
+        const Macro m = macro(C, s);
+        const float qs = s.rR * C.qc[0] + s.rB * C.qc[1];
+        a.aux[C.node_off + node] = make_float4(phase_field(C, s.rR, s.rB), m.ux * qs, m.uy * qs, m.uz * qs);
+    }
+}
+
+// --------------------------------------------------------------- k_ghost
+// One entry per wall-plane node and side.  The ghost phase field follows the
+// geometric wetting rule: across the half link to the ghost, rho^N changes by
+// cot(theta) |grad_par rho^N| (2D isotropic stencil on the first layer), so
+// that the interface meets the wall at theta through the red fluid.  Qbar,
+// which carries u (zero on the halfway wall), is reflected oddly.
+__global__ __launch_bounds__(256) void k_ghost(StepArgs a, const int2 *gtiles, int ngtiles)
+{
+    for (int t = blockIdx.x; t < ngtiles; t += gridDim.x) {
+        const int2 tl = gtiles[t];
+        const DevCase &C = a.cases[tl.x];
+        const int e = tl.y + (int)threadIdx.x;
+        if (e >= 2 * C.plane) continue;
+        const int side = e >= C.plane ? 1 : 0;
+        const int pi = e - side * C.plane;
+        int n[3] = {C.nx, C.ny, C.nz};
+        const int w = C.wall, b = w == 0 ? 1 : 0, cax = w == 2 ? 1 : 2;
+        const int ib = pi % n[b], ic = pi / n[b];
+        int q[3];
+        q[w] = side ? n[w] - 1 : 0;
+        float gb = 0.f, gc = 0.f;
+        #pragma unroll
+        for (int db = -1; db <= 1; ++db) {
+            #pragma unroll
+            for (int dc = -1; dc <= 1; ++dc) {
+                if (db == 0 && dc == 0) continue;
+                const float wgt = (db != 0 && dc != 0) ? (1.0f / 12.0f) : (1.0f / 3.0f);
+                int vb = ib + db, vc = ic + dc;
+                vb = vb < 0 ? n[b] - 1 : (vb >= n[b] ? 0 : vb);
+                vc = vc < 0 ? n[cax] - 1 : (vc >= n[cax] ? 0 : vc);
+                q[b] = vb; q[cax] = vc;
+                const float v = a.aux[C.node_off + q[0] + C.nx * (q[1] + C.ny * q[2])].x;
+                gb += wgt * (float)db * v;
+                gc += wgt * (float)dc * v;
+            }
+        }
+        q[b] = ib; q[cax] = ic;
+        const float4 s = a.aux[C.node_off + q[0] + C.nx * (q[1] + C.ny * q[2])];
+        const float gpar = sqrtf(gb * gb + gc * gc);
+        a.ghost[C.ghost_off + e] = make_float4(s.x + C.cot[side] * gpar, -s.y, -s.z, -s.w);
+    }
+}
+
+// Aux value at x + e (or the ghost beyond a wall).
+template <int X, int Y, int Z>
+__device__ inline float4 aux_at(const StepArgs &a, const DevCase &C, const Coord &c)
+{
+    const bool glo = (X == -1 && c.lo[0]) || (Y == -1 && c.lo[1]) || (Z == -1 && c.lo[2]);
+    const bool ghi = (X == 1 && c.hi[0]) || (Y == 1 && c.hi[1]) || (Z == 1 && c.hi[2]);
+    const int px = c.cx[1 + X], py = c.cy[1 + Y], pz = c.cz[1 + Z];
+    if (glo || ghi) {
+        const int gi = C.wall == 0 ? py + C.ny * pz : (C.wall == 1 ? px + C.nx * pz : px + C.nx * py);
+        return a.ghost[C.ghost_off + (ghi ? C.plane : 0) + gi];
+    }
+    return a.aux[C.node_off + px + C.nx * (py + C.ny * pz)];
+}
+
+// Eq. (49) for rho^N (all components) and for Qbar_alpha (component alpha only).
+struct Stencil { float gx, gy, gz, Qx, Qy, Qz; };
+
+template <int I = 1>
+__device__ inline void stencil_acc(const StepArgs &a, const DevCase &C, const Coord &c, Stencil &st)
+{
+    if constexpr (I < Q) {
+        constexpr int X = ex(I), Y = ey(I), Z = ez(I);
+        constexpr float w3 = ecls(I) == 1 ? (1.0f / 6.0f) : (1.0f / 12.0f);   // 3 w_i
+        const float4 v = aux_at<X, Y, Z>(a, C, c);
+        if constexpr (X != 0) { st.gx += (X * w3) * v.x; st.Qx += (X * w3) * v.y; }
+        if constexpr (Y != 0) { st.gy += (Y * w3) * v.x; st.Qy += (Y * w3) * v.z; }
+        if constexpr (Z != 0) { st.gz += (Z * w3) * v.x; st.Qz += (Z * w3) * v.w; }
+        stencil_acc<I + 1>(a, C, c, st);
+    }
+}
+
+// Eq. (52) with the quadratic joins (reading: harmonic mean at rho^N = 0,
+// zero slope where they meet tau_v^R / tau_v^B at +-delta).
+__device__ inline float tau_v(const DevCase &C, float rn)
+{
+    if (rn > C.delta) return C.tauR;
+    if (rn < -C.delta) return C.tauB;
+    if (rn > 0.f) return C.s1 + rn * (C.s2 + rn * C.s3);
+    return C.s1 + rn * (C.t2 + rn * C.t3);
+}
+
+// ------------------------------------------------------------- k_collide
+template <int ST>
+__global__ __launch_bounds__(256) void k_collide(StepArgs a)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const TileRange tr = tile_range(a.ntiles);
+    for (int t = tr.first; t < tr.end; t += tr.stride) {
+        const int2 tl = a.tiles[t];
+        const DevCase &C = a.cases[tl.x];
+        const int node = tl.y + (int)threadIdx.x;
+        if (node >= C.N) continue;
+        const Coord c = make_coord(C, node);
+        NodeState s;
+        pull_node<ST>(a, C, c, s);
+        const Macro M = macro(C, s);
+        const float ux = M.ux, uy = M.uy, uz = M.uz, rho = M.rho;
+
+        Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        stencil_acc(a, C, c, st);
+        const float rn = a.aux[C.node_off + node].x;
+        const float tv = tau_v(C, rn);
+        const float sv = 1.0f / tv, se = C.s_e, sq = C.s_q, sp = C.s_pi;
+
+        const float *f = s.f;
+        // raw moments m = M f (Eq. 43, Appendix), rows 4-18
+        const float d78 = f[7] + f[8], d910 = f[9] + f[10];
+        const float d1112 = f[11] + f[12], d1314 = f[13] + f[14];
+        const float d1516 = f[15] + f[16], d1718 = f[17] + f[18];
+        const float a12 = f[1] + f[2], a34 = f[3] + f[4], a56 = f[5] + f[6];
+        const float m16 = d78 + d910, m17 = d1112 + d1314, m18 = d1516 + d1718;
+        const float m4 = a12 + a34 + a56 + 2.0f * (m16 + m17 + m18);
+        const float m5 = 2.0f * a12 - a34 - a56 + m16 + m17 - 2.0f * m18;
+        const float m6 = a34 - a56 + m16 - m17;
+        const float m7 = d78 - d910, m8 = d1112 - d1314, m9 = d1516 - d1718;
+        const float m10 = f[7] - f[8] - f[9] + f[10];
+        const float m11 = f[7] - f[8] + f[9] - f[10];
+        const float m12 = f[11] - f[12] - f[13] + f[14];
+        const float m13 = f[11] - f[12] + f[13] - f[14];
+        const float m14 = f[15] - f[16] - f[17] + f[18];
+        const float m15 = f[15] - f[16] + f[17] - f[18];
+
+        // two-colour equilibria sum_k m^{k,eq} (Appendix rows 0-15; rows
+        // 16-18 as M f^eq), p = sum_k rho_k (c_s^k)^2
+        const float p = s.rR * C.cs2[0] + s.rB * C.cs2[1];
+        const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
+        const float e4 = 3.0f * p + rho * uu;
+        const float e5 = rho * (2.0f * uxx - uyy - uzz);
+        const float e6 = rho * (uyy - uzz);
+        const float e7 = rho * ux * uy, e8 = rho * ux * uz, e9 = rho * uy * uz;
+        const float p3 = C.improved ? p : rho * (1.0f / 3.0f);
+        const float e10 = p3 * uy, e11 = p3 * ux, e12 = p3 * uz;
+        const float e16b = (2.0f * p - rho * uu) * (1.0f / 6.0f);
+        const float e16 = e16b + 0.5f * rho * (uxx + uyy);
+        const float e17 = e16b + 0.5f * rho * (uxx + uzz);
+        const float e18 = e16b + 0.5f * rho * (uyy + uzz);
+
+        // correction term (Eq. 45), summed over the colours
+        float c4 = 0.f, c5 = 0.f, c6 = 0.f;
+        if (C.improved) {
+            c4 = st.Qx + st.Qy + st.Qz;
+            c5 = 2.0f * st.Qx - st.Qy - st.Qz;
+            c6 = st.Qy - st.Qz;
+        }
+        // body force in moment space (reading: Guo's source, M F^Guo)
+        const float Fx = M.Fx, Fy = M.Fy, Fz = M.Fz;
+        const float uFx = ux * Fx, uFy = uy * Fy, uFz = uz * Fz;
+        const float f4 = 2.0f * (uFx + uFy + uFz);
+        const float f5 = 2.0f * (2.0f * uFx - uFy - uFz);
+        const float f6 = 2.0f * (uFy - uFz);
+        const float f7 = ux * Fy + uy * Fx, f8 = ux * Fz + uz * Fx, f9 = uy * Fz + uz * Fy;
+        const float t3 = 1.0f / 3.0f;
+        const float f16 = (2.0f * uFx + 2.0f * uFy - uFz) * t3;
+        const float f17 = (2.0f * uFx - uFy + 2.0f * uFz) * t3;
+        const float f18 = (-uFx + 2.0f * uFy + 2.0f * uFz) * t3;
+        // perturbation in moment space: M Omega2 summed over the colours
+        // (Eq. 8), relaxed by S (Eq. 53)
+        const float g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
+        float o4 = 0.f, o5 = 0.f, o6 = 0.f, o7 = 0.f, o8 = 0.f, o9 = 0.f, o16 = 0.f, o17 = 0.f, o18 = 0.f;
+        float nx = 0.f, ny = 0.f, nz = 0.f;
+        if (g2 > 1e-24f) {
+            const float ig = rsqrtf(g2);
+            nx = st.gx * ig; ny = st.gy * ig; nz = st.gz * ig;
+            const float ag = C.Asum * ig * (1.0f / 9.0f);
+            const float gxx = st.gx * st.gx, gyy = st.gy * st.gy, gzz = st.gz * st.gz;
+            o4 = -2.0f * ag * g2;
+            o5 = ag * (3.0f * gxx - g2);
+            o6 = ag * (gyy - gzz);
+            o7 = ag * st.gx * st.gy; o8 = ag * st.gx * st.gz; o9 = ag * st.gy * st.gz;
+            o16 = -0.5f * ag * gzz; o17 = -0.5f * ag * gyy; o18 = -0.5f * ag * gxx;
+        }
+        // post-collision moment changes mbar (Eq. 41 + force + Eq. 53); rows
+        // 0-3: mass unchanged, momentum changed by F (exact for the sum)
+        const float he = 1.0f - 0.5f * se, hv = 1.0f - 0.5f * sv, hq = 1.0f - 0.5f * sq, hp = 1.0f - 0.5f * sp;
+        const float b4 = -se * (m4 - e4) + he * (c4 + f4) + se * o4;
+        const float b5 = -sv * (m5 - e5) + hv * (c5 + f5) + sv * o5;
+        const float b6 = -sv * (m6 - e6) + hv * (c6 + f6) + sv * o6;
+        const float b7 = -sv * (m7 - e7) + hv * f7 + sv * o7;
+        const float b8 = -sv * (m8 - e8) + hv * f8 + sv * o8;
+        const float b9 = -sv * (m9 - e9) + hv * f9 + sv * o9;
+        const float b10 = -sq * (m10 - e10) + hq * (Fy * t3);
+        const float b11 = -sq * (m11 - e11) + hq * (Fx * t3);
+        const float b12 = -sq * (m12 - e12) + hq * (Fz * t3);
+        const float b13 = -sq * (m13 - e11) + hq * (Fx * t3);
+        const float b14 = -sq * (m14 - e12) + hq * (Fz * t3);
+        const float b15 = -sq * (m15 - e10) + hq * (Fy * t3);
+        const float b16 = -sp * (m16 - e16) + hp * f16 + sp * o16;
+        const float b17 = -sp * (m17 - e17) + hp * f17 + sp * o17;
+        const float b18 = -sp * (m18 - e18) + hp * f18 + sp * o18;
+
+        // f* = f + M^-1 mbar (sparse closed form of M^-1)
+        float fs[Q];
+        const float q4 = b4 * (1.0f / 6.0f);
+        fs[0] = f[0] - b4 + b16 + b17 + b18;
+        {
+            const float base = q4 + b5 * (1.0f / 6.0f) - 0.5f * (b16 + b17);
+            const float odd = 0.5f * (Fx - b11 - b13);
+            fs[1] = f[1] + base + odd;
+            fs[2] = f[2] + base - odd;
+        }
+        {
+            const float base = q4 - b5 * (1.0f / 12.0f) + 0.25f * b6 - 0.5f * (b16 + b18);
+            const float odd = 0.5f * (Fy - b10 - b15);
+            fs[3] = f[3] + base + odd;
+            fs[4] = f[4] + base - odd;
+        }
+        {
+            const float base = q4 - b5 * (1.0f / 12.0f) - 0.25f * b6 - 0.5f * (b17 + b18);
+            const float odd = 0.5f * (Fz - b12 - b14);
+            fs[5] = f[5] + base + odd;
+            fs[6] = f[6] + base - odd;
+        }
+        fs[7] = f[7] + 0.25f * (b7 + b10 + b11 + b16);
+        fs[8] = f[8] + 0.25f * (b7 - b10 - b11 + b16);
+        fs[9] = f[9] + 0.25f * (-b7 - b10 + b11 + b16);
+        fs[10] = f[10] + 0.25f * (-b7 + b10 - b11 + b16);
+        fs[11] = f[11] + 0.25f * (b8 + b12 + b13 + b17);
+        fs[12] = f[12] + 0.25f * (b8 - b12 - b13 + b17);
+        fs[13] = f[13] + 0.25f * (-b8 - b12 + b13 + b17);
+        fs[14] = f[14] + 0.25f * (-b8 + b12 - b13 + b17);
+        fs[15] = f[15] + 0.25f * (b9 + b14 + b15 + b18);
+        fs[16] = f[16] + 0.25f * (b9 - b14 - b15 + b18);
+        fs[17] = f[17] + 0.25f * (-b9 - b14 + b15 + b18);
+        fs[18] = f[18] + 0.25f * (-b9 + b14 - b15 + b18);
+
+        // recoloring (Eq. 10-11): F0_i = sum_k rho_k phi_i^k is rho_R alpha_R +
+        // rho_B alpha_B at rest, p/6 on the axes and p/12 on the diagonals
+        const float ir = M.inv_rho;
+        const float ar = s.rR * ir;
+        const float bseg = C.beta * s.rR * s.rB * ir * ir;
+        const float sa = bseg * p * (1.0f / 6.0f);
+        const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
+        float seg[Q];
+        seg[0] = 0.f;
+        seg[1] = sa * nx; seg[2] = -sa * nx; seg[3] = sa * ny; seg[4] = -sa * ny;
+        seg[5] = sa * nz; seg[6] = -sa * nz;
+        seg[7] = sd * (nx + ny); seg[8] = -seg[7]; seg[9] = sd * (nx - ny); seg[10] = -seg[9];
+        seg[11] = sd * (nx + nz); seg[12] = -seg[11]; seg[13] = sd * (nx - nz); seg[14] = -seg[13];
+        seg[15] = sd * (ny + nz); seg[16] = -seg[15]; seg[17] = sd * (ny - nz); seg[18] = -seg[17];
+
+        T *outb = reinterpret_cast<T *>(a.fout) + C.pop_off;
+        const size_t N = (size_t)C.N;
+        #pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float fr = ar * fs[i] + seg[i];
+            const float fb = fs[i] - fr;
+            float shR = 0.f, shB = 0.f;
+            if constexpr (S::shifted) {
+                shR = s.rR * C.phi[0][ecls(i)];
+                shB = s.rB * C.phi[1][ecls(i)];
+            }
+            outb[(size_t)i * N + node] = S::enc(fr, shR, a.scale);
+            outb[(size_t)(Q + i) * N + node] = S::enc(fb, shB, a.scale);
+        }
+        if constexpr (S::shifted) a.rho_cur[C.node_off + node] = make_float2(s.rR, s.rB);
+    }
+}
+
+// ---------------------------------------------------------- diagnostics
+// Macroscopic fields of one case plus deterministic FP64 partial sums per
+// workgroup: {rho_R, rho_B, rho u_x, rho u_y, rho u_z, unstable-node count}.
+template <int ST>
+__global__ __launch_bounds__(256) void k_moments(StepArgs a, int tile0, float *rR, float *rB, float *rN,
+                                                 float *ux, float *uy, float *uz, double *partial)
+{
+    __shared__ double red[6][4];
+    const int2 tl = a.tiles[tile0 + blockIdx.x];
+    const DevCase &C = a.cases[tl.x];
+    const int node = tl.y + (int)threadIdx.x;
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    if (node < C.N) {
+        const Coord c = make_coord(C, node);
+        NodeState s;
+        pull_node<ST>(a, C, c, s);
+        const Macro m = macro(C, s);
+        if (rR) rR[node] = s.rR;
+        if (rB) rB[node] = s.rB;
+        if (rN) rN[node] = phase_field(C, s.rR, s.rB);
+        if (ux) ux[node] = m.ux;
+        if (uy) uy[node] = m.uy;
+        if (uz) uz[node] = m.uz;
+        v[0] = s.rR; v[1] = s.rB;
+        v[2] = (double)m.rho * m.ux; v[3] = (double)m.rho * m.uy; v[4] = (double)m.rho * m.uz;
+        const bool bad = !(isfinite(s.rR) && isfinite(s.rB) && isfinite(m.ux) && isfinite(m.uy) &&
+                           isfinite(m.uz)) || s.rR < C.neg_tol[0] || s.rB < C.neg_tol[1];
+        v[5] = bad ? 1.0 : 0.0;
+    }
+    // wavefront reduction (64 lanes), then across the 4 wavefronts
+    #pragma unroll
+    for (int k = 0; k < 6; ++k)
+        #pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+        #pragma unroll
+        for (int k = 0; k < 6; ++k) red[k][wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int nw = (blockDim.x + 63) / 64;
+        double acc = 0.0;
+        for (int w = 0; w < nw; ++w) acc += red[threadIdx.x][w];
+        partial[(size_t)blockIdx.x * 6 + threadIdx.x] = acc;
+    }
+}
+
+// Sum n partial 6-vectors in a fixed order (one workgroup of 256 lanes).
+__global__ __launch_bounds__(256) void k_reduce(const double *partial, int n, double *out)
+{
+    __shared__ double sh[6][256];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < n; b += blockDim.x)
+        #pragma unroll
+        for (int k = 0; k < 6; ++k) acc[k] += partial[(size_t)b * 6 + k];
+    #pragma unroll
+    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            #pragma unroll
+            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) out[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// ------------------------------------------------------------ utilities
+template <int I = 0>
+__device__ inline void map_all(const DevCase &C, const Coord &c, int64_t *sn, int8_t *sd)
+{
+    if constexpr (I < Q) {
+        int src, dir;
+        pull_source<I>(C, c, src, dir);
+        sn[(size_t)I * C.N + c.node] = src;
+        sd[(size_t)I * C.N + c.node] = (int8_t)dir;
+        map_all<I + 1>(C, c, sn, sd);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_index_map(const DevCase *cases, int cid, int64_t *sn, int8_t *sd)
+{
+    const DevCase &C = cases[cid];
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= C.N) return;
+    map_all(C, make_coord(C, node), sn, sd);
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const DevCase &C = a.cases[cid];
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= C.N) return;
+    const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+    const size_t N = (size_t)C.N;
+    float2 rp = make_float2(0.f, 0.f);
+    if constexpr (S::shifted) rp = a.rho_prev[C.node_off + node];
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        out[(size_t)i * N + node] = S::dec(base[(size_t)i * N + node], rp.x * C.phi[0][ecls(i)], a.inv_scale);
+        out[(size_t)(Q + i) * N + node] = S::dec(base[(size_t)(Q + i) * N + node], rp.y * C.phi[1][ecls(i)], a.inv_scale);
+    }
+}
+
+// Equilibrium start, Eq. (18) (improved) or Eq. (6) (original), evaluated in
+// FP64 and rounded once into the storage format.
+struct InitCase { double alpha[2]; int improved; };
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_init(StepArgs a, int cid, InitCase ic, const double *rR0,
+                                              const double *rB0, const double *ux0, const double *uy0,
+                                              const double *uz0)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const DevCase &C = a.cases[cid];
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= C.N) return;
+    const double r[2] = {rR0[node], rB0[node]};
+    const double u[3] = {ux0[node], uy0[node], uz0[node]};
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    T *base = reinterpret_cast<T *>(a.fout) + C.pop_off;
+    const size_t N = (size_t)C.N;
+    const float rf[2] = {(float)r[0], (float)r[1]};
+    #pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const double al = ic.alpha[k];
+        const double cs2 = 0.5 * (1.0 - al);
+        #pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cl = ecls(i);
+            const double w = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+            const double ph = cl == 0 ? al : (cl == 1 ? (1.0 - al) / 12.0 : (1.0 - al) / 24.0);
+            const double eu = ex(i) * u[0] + ey(i) * u[1] + ez(i) * u[2];
+            double br = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
+            if (ic.improved) br += 3.0 * eu * (3.0 * cs2 - 1.0) * (3.0 * cl - 5.0);
+            const double fe = r[k] * (ph + w * br);
+            T v;
+            if constexpr (S::shifted) v = (T)((fe - (double)(rf[k] * C.phi[k][cl])) * (double)a.scale);
+            else v = (T)fe;
+            base[(size_t)(k * Q + i) * N + node] = v;
+        }
+    }
+    if constexpr (S::shifted) a.rho_cur[C.node_off + node] = make_float2(rf[0], rf[1]);
+}
+
+}  // namespace lbcg

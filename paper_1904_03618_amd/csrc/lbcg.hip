@@ -1,0 +1,532 @@
+// lbcg.hip -- host side of the C ABI declared in include/lbcg.h: parameter
+// validation and derivation (FP64 on the host), device memory, tile tables,
+// kernel launches.  Every arithmetic step of the method runs in the kernels of
+// kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace lbcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHK(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(LBCG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr float kFp16Scale = 1024.0f;   // 2^10: typical deviations land in FP16's normal range
+
+}  // namespace
+
+struct lbcg_handle {
+    hipStream_t stream = nullptr;
+    int storage = LBCG_FP32, elem = 4, diag_every = 0, block = 256, persistent = 0;
+    int ncases = 0;
+    std::vector<DevCase> dc;
+    std::vector<int> tile_begin, tile_count;
+    DevCase *d_cases = nullptr;
+    int2 *d_tiles = nullptr, *d_gtiles = nullptr;
+    int ntiles = 0, ngtiles = 0;
+    void *pop[2] = {nullptr, nullptr};
+    int cur = 0;                       // pop[cur] holds the current level
+    float4 *aux = nullptr, *ghost = nullptr;
+    float2 *rho2[2] = {nullptr, nullptr};
+    double *partial = nullptr, *red = nullptr;
+    int64_t steps = 0, total_nodes = 0, total_pop = 0, total_ghost = 0;
+    float scale = 1.0f, inv_scale = 1.0f;
+    bool has_wall = false;
+    bool alive = true;
+    // kernel timing (lbcg_timing): event pool and pending (kernel, start, end)
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t ev_used = 0;
+    std::vector<int3> pending;
+    double ms_acc[3] = {0, 0, 0};
+    int64_t launches[3] = {0, 0, 0};
+};
+
+namespace {
+
+int validate(const lbcg_case &c, int idx)
+{
+    char buf[256];
+    auto bad = [&](const char *what) {
+        snprintf(buf, sizeof buf, "case %d: %s", idx, what);
+        return fail(LBCG_EINVAL, buf);
+    };
+    if (c.nx < 1 || c.ny < 1 || c.nz < 1) return bad("dimensions must be >= 1");
+    if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 30) return bad("more than 2^30 nodes in one case");
+    int walls = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (c.bc[a] != LBCG_PERIODIC && c.bc[a] != LBCG_WALL) return bad("bc must be PERIODIC or WALL");
+        walls += c.bc[a] == LBCG_WALL;
+    }
+    if (walls > 1) return bad("at most one wall axis is supported");
+    for (int k = 0; k < 2; ++k) {
+        if (!(c.alpha[k] >= 0.0 && c.alpha[k] < 1.0)) return bad("alpha must lie in [0, 1)");
+        if (!(c.rho_in[k] > 0.0)) return bad("rho_in must be > 0");
+        if (!(c.tau_v[k] > 0.5)) return bad("tau_v must be > 1/2");
+        if (!(c.theta_deg[k] > 0.0 && c.theta_deg[k] < 180.0)) return bad("theta must lie in (0, 180)");
+        if (!std::isfinite(c.A[k])) return bad("A must be finite");
+    }
+    if (!(c.tau_e > 0.5 && c.tau_q > 0.5 && c.tau_pi > 0.5)) return bad("tau_e, tau_q, tau_pi must be > 1/2");
+    if (!(c.delta > 0.0 && c.delta <= 1.0)) return bad("delta must lie in (0, 1]");
+    const double pR = c.rho_in[0] * (1.0 - c.alpha[0]), pB = c.rho_in[1] * (1.0 - c.alpha[1]);
+    if (std::fabs(pR - pB) > 1e-12 * std::max(pR, pB))
+        return bad("pressure balance rho_R^in (1 - alpha_R) = rho_B^in (1 - alpha_B) violated");
+    if (c.improved != 0 && c.improved != 1) return bad("improved must be 0 or 1");
+    return LBCG_OK;
+}
+
+DevCase derive(const lbcg_case &c)
+{
+    DevCase d;
+    std::memset(&d, 0, sizeof d);
+    d.nx = c.nx; d.ny = c.ny; d.nz = c.nz;
+    d.wall = -1;
+    for (int a = 0; a < 3; ++a)
+        if (c.bc[a] == LBCG_WALL) d.wall = a;
+    d.N = c.nx * c.ny * c.nz;
+    d.plane = d.wall < 0 ? 0 : d.N / (d.wall == 0 ? c.nx : (d.wall == 1 ? c.ny : c.nz));
+    d.improved = c.improved;
+    for (int k = 0; k < 2; ++k) {
+        const double al = c.alpha[k], cs2 = 0.5 * (1.0 - al);
+        d.rin_inv[k] = (float)(1.0 / c.rho_in[k]);
+        d.cs2[k] = (float)cs2;
+        d.qc[k] = (float)(1.0 - 3.0 * cs2);
+        d.phi[k][0] = (float)al;
+        d.phi[k][1] = (float)((1.0 - al) / 12.0);
+        d.phi[k][2] = (float)((1.0 - al) / 24.0);
+        d.neg_tol[k] = (float)(-1e-3 * c.rho_in[k]);
+        d.cot[k] = (float)std::tan((90.0 - c.theta_deg[k]) * M_PI / 180.0);
+    }
+    const double tR = c.tau_v[0], tB = c.tau_v[1], dl = c.delta;
+    const double s1 = 2.0 * tR * tB / (tR + tB), s2 = 2.0 * (tR - s1) / dl, s3 = -s2 / (2.0 * dl);
+    const double t2 = 2.0 * (s1 - tB) / dl, t3 = t2 / (2.0 * dl);
+    d.tauR = (float)tR; d.tauB = (float)tB;
+    d.s1 = (float)s1; d.s2 = (float)s2; d.s3 = (float)s3; d.t2 = (float)t2; d.t3 = (float)t3;
+    d.delta = (float)dl;
+    d.s_e = (float)(1.0 / c.tau_e); d.s_q = (float)(1.0 / c.tau_q); d.s_pi = (float)(1.0 / c.tau_pi);
+    d.Asum = (float)(c.A[0] + c.A[1]);
+    d.beta = (float)c.beta;
+    for (int a = 0; a < 3; ++a) { d.F[a] = (float)c.force[a]; d.g[a] = (float)c.grav[a]; }
+    d.rho_ref = (float)c.rho_ref;
+    return d;
+}
+
+StepArgs args_for(const lbcg_handle *h)
+{
+    StepArgs a;
+    a.fin = h->pop[h->cur];
+    a.fout = h->pop[h->cur ^ 1];
+    a.aux = h->aux;
+    a.ghost = h->ghost;
+    // level t was written with the densities of level t-1 (rho2[(t+1)&1]);
+    // the collision of level t records its own densities in rho2[t&1]
+    a.rho_prev = h->rho2[(h->steps + 1) & 1];
+    a.rho_cur = h->rho2[h->steps & 1];
+    a.cases = h->d_cases;
+    a.tiles = h->d_tiles;
+    a.ntiles = h->ntiles;
+    a.scale = h->scale;
+    a.inv_scale = h->inv_scale;
+    return a;
+}
+
+int next_event(lbcg_handle *h, hipEvent_t *ev, int *idx)
+{
+    if (h->ev_used == h->events.size()) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        h->events.push_back(e);
+    }
+    *idx = (int)h->ev_used++;
+    *ev = h->events[*idx];
+    return LBCG_OK;
+}
+
+// Record an event pair around launch() when timing is on.
+template <class F>
+int timed(lbcg_handle *h, int kernel, F &&launch)
+{
+    if (!h->timing) {
+        launch();
+        return LBCG_OK;
+    }
+    hipEvent_t e0, e1;
+    int i0, i1;
+    int rc = next_event(h, &e0, &i0);
+    if (!rc) rc = next_event(h, &e1, &i1);
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(e0, h->stream));
+    launch();
+    HIPCHK(hipEventRecord(e1, h->stream));
+    h->pending.push_back(make_int3(kernel, i0, i1));
+    return LBCG_OK;
+}
+
+template <int ST>
+int launch_step(lbcg_handle *h)
+{
+    StepArgs a = args_for(h);
+    const int grid = h->persistent > 0 ? h->persistent : h->ntiles;
+    int rc = timed(h, 0, [&] { hipLaunchKernelGGL(k_aux<ST>, dim3(grid), dim3(h->block), 0, h->stream, a); });
+    if (!rc && h->has_wall)
+        rc = timed(h, 1, [&] {
+            hipLaunchKernelGGL(k_ghost, dim3(std::min(h->ngtiles, 65536)), dim3(256), 0, h->stream, a,
+                               (const int2 *)h->d_gtiles, h->ngtiles);
+        });
+    if (!rc)
+        rc = timed(h, 2, [&] { hipLaunchKernelGGL(k_collide<ST>, dim3(grid), dim3(h->block), 0, h->stream, a); });
+    if (rc) return rc;
+    HIPCHK(hipGetLastError());
+    h->cur ^= 1;
+    h->steps += 1;
+    return LBCG_OK;
+}
+
+int step_once(lbcg_handle *h)
+{
+    switch (h->storage) {
+    case LBCG_FP32: return launch_step<LBCG_FP32>(h);
+    case LBCG_FP16S: return launch_step<LBCG_FP16S>(h);
+    default: return launch_step<LBCG_BF16S>(h);
+    }
+}
+
+// FP64 sums over tiles [t0, t0 + nt) into h->red[0..5]; optional field exports.
+template <int ST>
+int moments_impl(lbcg_handle *h, int t0, int nt, float *rR, float *rB, float *rN, float *ux, float *uy,
+                 float *uz)
+{
+    StepArgs a = args_for(h);
+    hipLaunchKernelGGL(k_moments<ST>, dim3(nt), dim3(h->block), 0, h->stream, a, t0, rR, rB, rN, ux, uy, uz,
+                       h->partial);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, h->stream, (const double *)h->partial, nt, h->red);
+    HIPCHK(hipGetLastError());
+    return LBCG_OK;
+}
+
+int moments_any(lbcg_handle *h, int t0, int nt, float *rR, float *rB, float *rN, float *ux, float *uy,
+                float *uz)
+{
+    switch (h->storage) {
+    case LBCG_FP32: return moments_impl<LBCG_FP32>(h, t0, nt, rR, rB, rN, ux, uy, uz);
+    case LBCG_FP16S: return moments_impl<LBCG_FP16S>(h, t0, nt, rR, rB, rN, ux, uy, uz);
+    default: return moments_impl<LBCG_BF16S>(h, t0, nt, rR, rB, rN, ux, uy, uz);
+    }
+}
+
+int stability_check(lbcg_handle *h)
+{
+    int rc = moments_any(h, 0, h->ntiles, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (rc) return rc;
+    double out[6];
+    HIPCHK(hipMemcpyAsync(out, h->red, sizeof out, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (out[5] != 0.0 || !std::isfinite(out[0]) || !std::isfinite(out[1]))
+        return fail(LBCG_EUNSTABLE, "unstable state (NaN/Inf or negative colour density) at step " +
+                                        std::to_string(h->steps));
+    return LBCG_OK;
+}
+
+void release(lbcg_handle *h)
+{
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+    h->events.clear();
+    (void)hipFree(h->d_cases);
+    (void)hipFree(h->d_tiles);
+    (void)hipFree(h->d_gtiles);
+    (void)hipFree(h->pop[0]);
+    (void)hipFree(h->pop[1]);
+    (void)hipFree(h->aux);
+    (void)hipFree(h->ghost);
+    (void)hipFree(h->rho2[0]);
+    (void)hipFree(h->rho2[1]);
+    (void)hipFree(h->partial);
+    (void)hipFree(h->red);
+}
+
+template <int ST>
+int init_case(lbcg_handle *h, int cid, const lbcg_case &c, const lbcg_fields &f)
+{
+    const int64_t N = h->dc[cid].N;
+    const double *src[5] = {f.rhoR, f.rhoB, f.ux, f.uy, f.uz};
+    double *dev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *tmp = nullptr;
+    if (!f.on_device) {
+        if (hipMalloc(&tmp, sizeof(double) * 5 * N) != hipSuccess) return fail(LBCG_ENOMEM, "init staging");
+        for (int q = 0; q < 5; ++q) {
+            dev[q] = tmp + q * N;
+            if (hipMemcpyAsync(dev[q], src[q], sizeof(double) * N, hipMemcpyHostToDevice, h->stream) !=
+                hipSuccess) {
+                (void)hipFree(tmp);
+                return fail(LBCG_EDEVICE, "init field copy");
+            }
+        }
+    } else {
+        for (int q = 0; q < 5; ++q) dev[q] = const_cast<double *>(src[q]);
+    }
+    StepArgs a = args_for(h);
+    a.fout = h->pop[h->cur];                 // level 0 is written into the current buffer
+    a.rho_cur = h->rho2[1];                  // and decoded with rho2[(0 + 1) & 1]
+    InitCase ic{{c.alpha[0], c.alpha[1]}, c.improved};
+    hipLaunchKernelGGL(k_init<ST>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, h->stream, a, cid, ic,
+                       (const double *)dev[0], (const double *)dev[1], (const double *)dev[2],
+                       (const double *)dev[3], (const double *)dev[4]);
+    hipError_t e = hipGetLastError();
+    if (tmp) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(tmp);
+    }
+    if (e != hipSuccess) return fail(LBCG_EDEVICE, std::string("k_init: ") + hipGetErrorString(e));
+    return LBCG_OK;
+}
+
+int init_any(lbcg_handle *h, int cid, const lbcg_case &c, const lbcg_fields &f)
+{
+    switch (h->storage) {
+    case LBCG_FP32: return init_case<LBCG_FP32>(h, cid, c, f);
+    case LBCG_FP16S: return init_case<LBCG_FP16S>(h, cid, c, f);
+    default: return init_case<LBCG_BF16S>(h, cid, c, f);
+    }
+}
+
+int check_handle(const lbcg_handle *h)
+{
+    if (!h || !h->alive) return fail(LBCG_ESTATE, "invalid or freed handle");
+    return LBCG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lbcg_last_error(void) { return g_err.c_str(); }
+
+int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, const lbcg_options *opt,
+              void *hip_stream, lbcg_handle **out)
+{
+    g_err.clear();
+    if (!out) return fail(LBCG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!cases || !init || n_cases < 1) return fail(LBCG_EINVAL, "cases/init NULL or n_cases < 1");
+    lbcg_options o = {LBCG_FP32, 0, 256, 0};
+    if (opt) o = *opt;
+    if (o.storage != LBCG_FP32 && o.storage != LBCG_FP16S && o.storage != LBCG_BF16S)
+        return fail(LBCG_EINVAL, "unknown storage format");
+    if (o.block_nodes == 0) o.block_nodes = 256;
+    if (o.block_nodes < 64 || o.block_nodes > 256 || o.block_nodes % 64)
+        return fail(LBCG_EINVAL, "block_nodes must be 64, 128, 192 or 256");
+    if (o.diag_every < 0 || o.persistent_blocks < 0) return fail(LBCG_EINVAL, "negative option");
+    for (int c = 0; c < n_cases; ++c) {
+        int rc = validate(cases[c], c);
+        if (rc) return rc;
+        const lbcg_fields &f = init[c];
+        if (!f.rhoR || !f.rhoB || !f.ux || !f.uy || !f.uz) return fail(LBCG_EINVAL, "NULL init field");
+    }
+
+    lbcg_handle *h = new lbcg_handle();
+    h->stream = (hipStream_t)hip_stream;
+    h->storage = o.storage;
+    h->elem = o.storage == LBCG_FP32 ? 4 : 2;
+    h->diag_every = o.diag_every;
+    h->block = o.block_nodes;
+    h->persistent = o.persistent_blocks;
+    h->ncases = n_cases;
+    h->scale = o.storage == LBCG_FP16S ? kFp16Scale : 1.0f;
+    h->inv_scale = 1.0f / h->scale;
+
+    std::vector<int2> tiles, gtiles;
+    for (int c = 0; c < n_cases; ++c) {
+        DevCase d = derive(cases[c]);
+        d.pop_off = h->total_pop;
+        d.node_off = h->total_nodes;
+        d.ghost_off = h->total_ghost;
+        h->total_pop += (int64_t)2 * Q * d.N;
+        h->total_nodes += d.N;
+        h->total_ghost += (int64_t)2 * d.plane;
+        if (d.wall >= 0) h->has_wall = true;
+        h->tile_begin.push_back((int)tiles.size());
+        for (int n0 = 0; n0 < d.N; n0 += h->block) tiles.push_back(make_int2(c, n0));
+        h->tile_count.push_back((int)tiles.size() - h->tile_begin.back());
+        for (int e0 = 0; e0 < 2 * d.plane; e0 += 256) gtiles.push_back(make_int2(c, e0));
+        h->dc.push_back(d);
+    }
+    h->ntiles = (int)tiles.size();
+    h->ngtiles = (int)gtiles.size();
+
+    auto alloc = [&](void **p, size_t bytes) {
+        if (bytes == 0) bytes = 256;
+        return hipMalloc(p, bytes) == hipSuccess;
+    };
+    bool ok = alloc((void **)&h->d_cases, sizeof(DevCase) * n_cases) &&
+              alloc((void **)&h->d_tiles, sizeof(int2) * tiles.size()) &&
+              alloc((void **)&h->d_gtiles, sizeof(int2) * std::max<size_t>(1, gtiles.size())) &&
+              alloc(&h->pop[0], (size_t)h->elem * h->total_pop) &&
+              alloc(&h->pop[1], (size_t)h->elem * h->total_pop) &&
+              alloc((void **)&h->aux, sizeof(float4) * h->total_nodes) &&
+              alloc((void **)&h->ghost, sizeof(float4) * std::max<int64_t>(1, h->total_ghost)) &&
+              alloc((void **)&h->partial, sizeof(double) * 6 * (size_t)h->ntiles) &&
+              alloc((void **)&h->red, sizeof(double) * 8);
+    if (ok && h->storage != LBCG_FP32)
+        ok = alloc((void **)&h->rho2[0], sizeof(float2) * h->total_nodes) &&
+             alloc((void **)&h->rho2[1], sizeof(float2) * h->total_nodes);
+    if (!ok) {
+        release(h);
+        delete h;
+        return fail(LBCG_ENOMEM, "device allocation failed");
+    }
+    int rc = LBCG_OK;
+    if (hipMemcpyAsync(h->d_cases, h->dc.data(), sizeof(DevCase) * n_cases, hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice,
+                       h->stream) != hipSuccess ||
+        (!gtiles.empty() && hipMemcpyAsync(h->d_gtiles, gtiles.data(), sizeof(int2) * gtiles.size(),
+                                           hipMemcpyHostToDevice, h->stream) != hipSuccess))
+        rc = fail(LBCG_EDEVICE, "table upload failed");
+    for (int c = 0; c < n_cases && rc == LBCG_OK; ++c) rc = init_any(h, c, cases[c], init[c]);
+    if (rc == LBCG_OK && hipStreamSynchronize(h->stream) != hipSuccess)
+        rc = fail(LBCG_EDEVICE, "synchronise after init failed");
+    if (rc != LBCG_OK) {
+        release(h);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return LBCG_OK;
+}
+
+int lbcg_step(lbcg_handle *h, int64_t nsteps)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (nsteps < 0) return fail(LBCG_EINVAL, "nsteps < 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        rc = step_once(h);
+        if (rc) return rc;
+        if (h->diag_every > 0 && h->steps % h->diag_every == 0) {
+            rc = stability_check(h);
+            if (rc) return rc;
+        }
+    }
+    return LBCG_OK;
+}
+
+int lbcg_moments(lbcg_handle *h, int32_t case_id, float *rhoR, float *rhoB, float *rhoN, float *ux, float *uy,
+                 float *uz, double *diag)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (case_id < 0 || case_id >= h->ncases) return fail(LBCG_EINVAL, "case_id out of range");
+    rc = moments_any(h, h->tile_begin[case_id], h->tile_count[case_id], rhoR, rhoB, rhoN, ux, uy, uz);
+    if (rc) return rc;
+    if (diag) {
+        double out[6];
+        HIPCHK(hipMemcpyAsync(out, h->red, sizeof out, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int k = 0; k < 5; ++k) diag[k] = out[k];
+    }
+    return LBCG_OK;
+}
+
+int lbcg_free(lbcg_handle *h)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    (void)hipStreamSynchronize(h->stream);
+    release(h);
+    h->alive = false;
+    delete h;
+    return LBCG_OK;
+}
+
+int64_t lbcg_steps_done(const lbcg_handle *h) { return h ? h->steps : -1; }
+
+int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id)
+{
+    if (!h || case_id < 0 || case_id >= h->ncases) return -1;
+    return h->dc[case_id].N;
+}
+
+int32_t lbcg_storage_bytes(const lbcg_handle *h) { return h ? h->elem : -1; }
+
+int lbcg_timing(lbcg_handle *h, int32_t enable)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    h->timing = enable != 0;
+    return LBCG_OK;
+}
+
+int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!ms || !launches) return fail(LBCG_EINVAL, "NULL output");
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (const int3 &p : h->pending) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, h->events[p.y], h->events[p.z]));
+        h->ms_acc[p.x] += t;
+        h->launches[p.x] += 1;
+    }
+    h->pending.clear();
+    h->ev_used = 0;
+    for (int k = 0; k < 3; ++k) {
+        ms[k] = h->ms_acc[k];
+        launches[k] = h->launches[k];
+        h->ms_acc[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    return LBCG_OK;
+}
+
+int lbcg_index_map(lbcg_handle *h, int32_t case_id, int64_t *src_node, int8_t *src_dir)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (case_id < 0 || case_id >= h->ncases || !src_node || !src_dir) return fail(LBCG_EINVAL, "bad argument");
+    const int N = h->dc[case_id].N;
+    hipLaunchKernelGGL(k_index_map, dim3((N + 255) / 256), dim3(256), 0, h->stream, (const DevCase *)h->d_cases,
+                       case_id, src_node, src_dir);
+    HIPCHK(hipGetLastError());
+    return LBCG_OK;
+}
+
+int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (case_id < 0 || case_id >= h->ncases || !f) return fail(LBCG_EINVAL, "bad argument");
+    const int N = h->dc[case_id].N;
+    StepArgs a = args_for(h);
+    dim3 g((N + 255) / 256), b(256);
+    switch (h->storage) {
+    case LBCG_FP32: hipLaunchKernelGGL(k_get_pop<LBCG_FP32>, g, b, 0, h->stream, a, case_id, f); break;
+    case LBCG_FP16S: hipLaunchKernelGGL(k_get_pop<LBCG_FP16S>, g, b, 0, h->stream, a, case_id, f); break;
+    default: hipLaunchKernelGGL(k_get_pop<LBCG_BF16S>, g, b, 0, h->stream, a, case_id, f); break;
+    }
+    HIPCHK(hipGetLastError());
+    return LBCG_OK;
+}
+
+}  // extern "C"

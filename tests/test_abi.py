@@ -1,0 +1,92 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point include/lbcg.h declares, and rejects invalid arguments
+before touching the device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1904_03618_amd import lbcg as B
+from paper_1904_03618_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "lbcg.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbcg_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.load()
+    names = header_functions()
+    assert {"lbcg_init", "lbcg_step", "lbcg_moments", "lbcg_free"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    # 6 ints + 10 doubles (5 pairs) + 5 doubles + 7 doubles + 2 ints
+    assert C.sizeof(B.lbcg_case) == 6 * 4 + 10 * 8 + 5 * 8 + 7 * 8 + 2 * 4
+    assert C.sizeof(B.lbcg_fields) == 5 * 8 + 8
+    assert C.sizeof(B.lbcg_options) == 16
+
+
+def _init_rc(p, fl=None, opt=None, n=1):
+    L = B.load()
+    if fl is None:
+        N = p["nx"] * p["ny"] * p["nz"]
+        fl = {k: np.zeros(N) for k in ("rhoR", "rhoB", "ux", "uy", "uz")}
+    cs = (B.lbcg_case * n)(*[B.pack_case(p)] * n)
+    fs = (B.lbcg_fields * n)()
+    keep = [np.ascontiguousarray(fl[k], dtype=np.float64) for k in ("rhoR", "rhoB", "ux", "uy", "uz")]
+    for i in range(n):
+        fs[i].rhoR, fs[i].rhoB, fs[i].ux, fs[i].uy, fs[i].uz = [a.ctypes.data for a in keep]
+    h = C.c_void_p()
+    o = opt if opt is not None else B.lbcg_options(0, 0, 0, 0)
+    rc = L.lbcg_init(cs, n, fs, C.byref(o), None, C.byref(h))
+    return rc, h.value
+
+
+@pytest.mark.parametrize("change,frag", [
+    (dict(nx=0), "dimensions"),
+    (dict(bc=(1, 0, 1)), "one wall axis"),
+    (dict(alpha=(1.0, 0.7)), "alpha"),
+    (dict(tau_v=(0.5, 0.7)), "tau_v"),
+    (dict(tau_q=0.4), "tau_e"),
+    (dict(rho_in=(3.0, 1.1)), "pressure balance"),
+    (dict(rho_in=(-1.0, 1.0)), "rho_in"),
+    (dict(theta_deg=(0.0, 90.0)), "theta"),
+    (dict(improved=2), "improved"),
+])
+def test_init_rejects_invalid_parameters(change, frag):
+    p, _ = W.paper_fluids_droplet(4, 1.0)
+    p = dict(p, **change)
+    rc, h = _init_rc(p)
+    assert rc == B.LBCG_EINVAL and h is None
+    assert frag in B.lbcg_last_error()
+
+
+def test_init_rejects_bad_options_and_pointers():
+    p, _ = W.paper_fluids_droplet(4, 1.0)
+    rc, _ = _init_rc(p, opt=B.lbcg_options(7, 0, 0, 0))
+    assert rc == B.LBCG_EINVAL and "storage" in B.lbcg_last_error()
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 96 + 1, 0))
+    assert rc == B.LBCG_EINVAL and "block_nodes" in B.lbcg_last_error()
+    L = B.load()
+    h = C.c_void_p()
+    assert L.lbcg_init(None, 1, None, None, None, C.byref(h)) == B.LBCG_EINVAL
+    assert L.lbcg_init(None, 1, None, None, None, None) == B.LBCG_EINVAL
+
+
+def test_calls_on_null_handle_fail_cleanly():
+    L = B.load()
+    assert L.lbcg_step(None, 1) == B.LBCG_ESTATE
+    assert L.lbcg_free(None) == B.LBCG_ESTATE
+    assert L.lbcg_moments(None, 0, None, None, None, None, None, None, None) == B.LBCG_ESTATE
+    assert L.lbcg_steps_done(None) == -1
+    assert L.lbcg_case_nodes(None, 0) == -1

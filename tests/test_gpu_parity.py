@@ -1,0 +1,152 @@
+"""Parity of the gfx950 path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (FP32 storage, after the stated number of steps): max-abs 1e-5 on
+the phase field rho^N and 1e-6 on the velocity (lattice units); densities
+1e-5 relative to rho^in.  Index maps are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import gpu_run, max_err, oracle_run, report
+from paper_1904_03618_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_N, TOL_U, TOL_RHO = 1e-5, 1e-6, 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_03618_amd import lbcg as B
+    B.load()
+
+
+def assert_parity(tag, g, o, p, tn=TOL_N, tu=TOL_U, tr=TOL_RHO):
+    e = max_err(g, o)
+    report(tag, e)
+    assert e["rhoN"] <= tn, e
+    assert max(e["ux"], e["uy"], e["uz"]) <= tu, e
+    assert e["rhoR"] <= tr * p["rho_in"][0] and e["rhoB"] <= tr * p["rho_in"][1], e
+
+
+@pytest.mark.parametrize("dims,bc", [((3, 4, 5), (0, 0, 0)), ((1, 1, 7), (0, 0, 1)), ((5, 2, 3), (0, 1, 0)),
+                                     ((4, 3, 2), (1, 0, 0)), ((2, 3, 1), (0, 0, 0)), ((7, 5, 9), (0, 0, 1)),
+                                     ((64, 3, 2), (0, 0, 1))])
+def test_index_map_bit_exact(dims, bc):
+    from oracle import oracle as O
+    from paper_1904_03618_amd import lbcg as B
+    p, fl = W.random_state_case(*dims, seed=3, bc=bc)
+    h = B.lbcg_init([(p, fl)])
+    try:
+        sn, sd = B.lbcg_index_map(h, 0)
+        on, od = O.index_map(p)
+        assert np.array_equal(sn.cpu().numpy(), on)
+        assert np.array_equal(sd.cpu().numpy(), od)
+    finally:
+        B.lbcg_free(h)
+
+
+def test_initial_level_matches_oracle():
+    p, fl = W.random_state_case(9, 7, 6, seed=2, bc=(0, 0, 1))
+    g = gpu_run([(p, fl)], 0)[0]
+    o = oracle_run(p, fl, 0)
+    assert_parity("level0", g, o, p, tn=1e-6, tu=1e-7, tr=1e-6)
+    assert np.allclose(g["diag"], o["diag"], rtol=1e-6, atol=1e-9)
+
+
+def _cases():
+    return {
+        "static_droplet_32": lambda: W.static_droplet(32, 8.0),
+        "paper_fluids_32": lambda: W.paper_fluids_droplet(32, 8.0),
+        "galilean_24": lambda: W.galilean_droplet(24, 5.0, seed=7),
+        "channel_8x8x32": lambda: W.layered_channel(8, 8, 32, ratio=10.0, visc_ratio=10.0, G=1e-5),
+        "rayleigh_taylor_12": lambda: W.rayleigh_taylor(12, g=2e-4),
+        "walls_wetting_force": lambda: W.random_state_case(14, 12, 11, seed=5, bc=(0, 0, 1),
+                                                           theta=(65.0, 140.0), force=(2e-5, 0, -1e-5)),
+        "original_model": lambda: W.random_state_case(12, 10, 9, seed=6, improved=0, bc=(0, 1, 0)),
+        "wall_x_buoyancy": lambda: W.random_state_case(11, 9, 8, seed=9, bc=(1, 0, 0), theta=(100.0, 80.0),
+                                                       grav=(1e-4, 0, 0), rho_ref=2.0),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_parity_500_steps(name):
+    p, fl = _cases()[name]()
+    steps = 500
+    g = gpu_run([(p, fl)], steps)[0]
+    o = oracle_run(p, fl, steps)
+    assert_parity(name, g, o, p)
+
+
+def test_batched_cases_match_oracle_and_single_runs():
+    """Several uneven boxes with different fluids and contact angles in one
+    handle (one launch per kernel): each equals its single-case run bit for
+    bit and the oracle within tolerance."""
+    cases = [W.impact_case(c, lmin=9, lmax=16) for c in range(4)]
+    steps = 200
+    batch = gpu_run(cases, steps, persistent_blocks=64)
+    for c, (p, fl) in enumerate(cases):
+        alone = gpu_run([(p, fl)], steps)[0]
+        for k in ("rhoR", "rhoB", "ux", "uy", "uz"):
+            assert np.array_equal(batch[c][k], alone[k]), (c, k)
+        o = oracle_run(p, fl, steps)
+        assert_parity(f"impact{c}", batch[c], o, p)
+
+
+def test_tile_shape_does_not_change_result():
+    """No atomics in the step: tile size and persistent scheduling give
+    bitwise identical populations."""
+    import torch
+    from paper_1904_03618_amd import lbcg as B
+    p, fl = W.random_state_case(20, 13, 7, seed=4, bc=(0, 0, 1))
+    ref = None
+    for opt in (dict(block_nodes=256), dict(block_nodes=64), dict(block_nodes=128, persistent_blocks=40)):
+        h = B.lbcg_init([(p, fl)], **opt)
+        try:
+            B.lbcg_step(h, 40)
+            f = B.lbcg_get_populations(h, 0).cpu().numpy()
+            torch.cuda.synchronize()
+        finally:
+            B.lbcg_free(h)
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(ref, f), opt
+
+
+def test_full_size_galilean_128():
+    """128^3 Galilean droplet in the launch configuration the benchmark times:
+    every node against the oracle after 3 steps; FP64 mass and momentum sums
+    after 200 steps."""
+    p, fl = W.galilean_droplet(128, 20.0, seed=1904)
+    g = gpu_run([(p, fl)], 3)[0]
+    o = oracle_run(p, fl, 3)
+    assert_parity("galilean128_3", g, o, p, tn=1e-6, tu=1e-7, tr=1e-6)
+    g2 = gpu_run([(p, fl)], 200)[0]
+    d0 = o["diag"]
+    rel = np.abs(g2["diag"][:2] - d0[:2]) / d0[:2]
+    print("galilean128 mass drift after 200 steps", rel, flush=True)
+    assert rel.max() < 1e-5
+    assert np.allclose(g2["diag"][2:], d0[2:], rtol=1e-4)
+
+
+def test_unstable_state_is_reported():
+    """A NaN in the initial velocity (set on the host) makes the periodic
+    stability check return LBCG_EUNSTABLE at the first check."""
+    from paper_1904_03618_amd import lbcg as B
+    p, fl = W.random_state_case(6, 5, 4, seed=1)
+    fl = dict(fl)
+    ux = fl["ux"].copy()
+    ux[7] = np.nan
+    fl["ux"] = ux
+    h = B.lbcg_init([(p, fl)], diag_every=2)
+    try:
+        with pytest.raises(B.LbcgError) as ei:
+            B.lbcg_step(h, 10)
+        assert ei.value.code == B.LBCG_EUNSTABLE
+        assert B.lbcg_steps_done(h) == 2
+    finally:
+        B.lbcg_free(h)
