@@ -520,65 +520,92 @@ __global__ __launch_bounds__(256) void k_index_map(const DevCase *cases, int cid
     map_all(C, make_coord(C, node), sn, sd);
 }
 
-template <int ST>
-__global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out)
+// Current-level populations f_i^k(x) (the values the next collision sees):
+// the pull of every direction, decoded to FP32.
+template <int ST, int I = 0>
+__device__ inline void get_dirs(const StepArgs &a, const DevCase &C, const Coord &c, float *out)
 {
-    using S = Storage<ST>;
-    using T = typename S::T;
-    const DevCase &C = a.cases[cid];
-    const int node = blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= C.N) return;
-    const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
-    const size_t N = (size_t)C.N;
-    float2 rp = make_float2(0.f, 0.f);
-    if constexpr (S::shifted) rp = a.rho_prev[C.node_off + node];
-    #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        out[(size_t)i * N + node] = S::dec(base[(size_t)i * N + node], rp.x * C.phi[0][ecls(i)], a.inv_scale);
-        out[(size_t)(Q + i) * N + node] = S::dec(base[(size_t)(Q + i) * N + node], rp.y * C.phi[1][ecls(i)], a.inv_scale);
+    if constexpr (I < Q) {
+        using S = Storage<ST>;
+        using T = typename S::T;
+        int src, dir;
+        pull_source<I>(C, c, src, dir);
+        const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+        const size_t N = (size_t)C.N;
+        float2 rp = make_float2(0.f, 0.f);
+        if constexpr (S::shifted) rp = a.rho_prev[C.node_off + src];
+        out[(size_t)I * N + c.node] = S::dec(base[(size_t)dir * N + src], rp.x * C.phi[0][ecls(I)], a.inv_scale);
+        out[(size_t)(Q + I) * N + c.node] =
+            S::dec(base[(size_t)(Q + dir) * N + src], rp.y * C.phi[1][ecls(I)], a.inv_scale);
+        get_dirs<ST, I + 1>(a, C, c, out);
     }
 }
 
+template <int ST>
+__global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out)
+{
+    const DevCase &C = a.cases[cid];
+    const int node = blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= C.N) return;
+    get_dirs<ST>(a, C, make_coord(C, node), out);
+}
+
 // Equilibrium start, Eq. (18) (improved) or Eq. (6) (original), evaluated in
-// FP64 and rounded once into the storage format.
+// FP64 and rounded once into the storage format.  The buffers hold values that
+// the next pull reads, so f_i^{k,eq}(y) is stored in the slot the pull of
+// (y, i) reads: (src, dir) of pull_source, which is a permutation of all
+// slots.  A shifted slot at src is encoded relative to rho_k(src) phi_i^k.
 struct InitCase { double alpha[2]; int improved; };
+
+template <int ST, int I = 0>
+__device__ inline void init_dirs(const StepArgs &a, const DevCase &C, const Coord &c, const InitCase &ic,
+                                 const double (&r)[2], const double (&u)[3], double uu, const double *rR0,
+                                 const double *rB0)
+{
+    if constexpr (I < Q) {
+        using S = Storage<ST>;
+        using T = typename S::T;
+        constexpr int cl = ecls(I);
+        int src, dir;
+        pull_source<I>(C, c, src, dir);
+        T *base = reinterpret_cast<T *>(a.fout) + C.pop_off;
+        const size_t N = (size_t)C.N;
+        const double eu = ex(I) * u[0] + ey(I) * u[1] + ez(I) * u[2];
+        const double w = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+        #pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const double al = ic.alpha[k];
+            const double cs2 = 0.5 * (1.0 - al);
+            const double ph = cl == 0 ? al : (cl == 1 ? (1.0 - al) / 12.0 : (1.0 - al) / 24.0);
+            double br = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
+            if (ic.improved) br += 3.0 * eu * (3.0 * cs2 - 1.0) * (3.0 * cl - 5.0);
+            const double fe = r[k] * (ph + w * br);
+            T v;
+            if constexpr (S::shifted) {
+                const float rs = (float)(k == 0 ? rR0[src] : rB0[src]);
+                v = (T)((fe - (double)(rs * C.phi[k][cl])) * (double)a.scale);
+            } else {
+                v = (T)fe;
+            }
+            base[(size_t)(k * Q + dir) * N + src] = v;
+        }
+        init_dirs<ST, I + 1>(a, C, c, ic, r, u, uu, rR0, rB0);
+    }
+}
 
 template <int ST>
 __global__ __launch_bounds__(256) void k_init(StepArgs a, int cid, InitCase ic, const double *rR0,
                                               const double *rB0, const double *ux0, const double *uy0,
                                               const double *uz0)
 {
-    using S = Storage<ST>;
-    using T = typename S::T;
     const DevCase &C = a.cases[cid];
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= C.N) return;
     const double r[2] = {rR0[node], rB0[node]};
     const double u[3] = {ux0[node], uy0[node], uz0[node]};
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    T *base = reinterpret_cast<T *>(a.fout) + C.pop_off;
-    const size_t N = (size_t)C.N;
-    const float rf[2] = {(float)r[0], (float)r[1]};
-    #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const double al = ic.alpha[k];
-        const double cs2 = 0.5 * (1.0 - al);
-        #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int cl = ecls(i);
-            const double w = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
-            const double ph = cl == 0 ? al : (cl == 1 ? (1.0 - al) / 12.0 : (1.0 - al) / 24.0);
-            const double eu = ex(i) * u[0] + ey(i) * u[1] + ez(i) * u[2];
-            double br = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
-            if (ic.improved) br += 3.0 * eu * (3.0 * cs2 - 1.0) * (3.0 * cl - 5.0);
-            const double fe = r[k] * (ph + w * br);
-            T v;
-            if constexpr (S::shifted) v = (T)((fe - (double)(rf[k] * C.phi[k][cl])) * (double)a.scale);
-            else v = (T)fe;
-            base[(size_t)(k * Q + i) * N + node] = v;
-        }
-    }
-    if constexpr (S::shifted) a.rho_cur[C.node_off + node] = make_float2(rf[0], rf[1]);
+    init_dirs<ST>(a, C, make_coord(C, node), ic, r, u, uu, rR0, rB0);
+    if constexpr (Storage<ST>::shifted) a.rho_cur[C.node_off + node] = make_float2((float)r[0], (float)r[1]);
 }
 
 }  // namespace lbcg

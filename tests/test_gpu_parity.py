@@ -57,6 +57,16 @@ def test_initial_level_matches_oracle():
     assert np.allclose(g["diag"], o["diag"], rtol=1e-6, atol=1e-9)
 
 
+@pytest.mark.parametrize("improved", [1, 0])
+@pytest.mark.parametrize("bc", [(0, 0, 0), (0, 0, 1)])
+def test_one_step_matches_oracle(improved, bc):
+    """A single step from a smooth random state: FP32 rounding only."""
+    p, fl = W.random_state_case(13, 11, 9, seed=12, bc=bc, improved=improved, force=(1e-4, -2e-4, 5e-5))
+    g = gpu_run([(p, fl)], 1)[0]
+    o = oracle_run(p, fl, 1)
+    assert_parity(f"one_step_{improved}_{bc}", g, o, p, tn=1e-6, tu=1e-7, tr=1e-6)
+
+
 def _cases():
     return {
         "static_droplet_32": lambda: W.static_droplet(32, 8.0),
