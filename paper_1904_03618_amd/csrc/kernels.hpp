@@ -401,8 +401,10 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 
         // recoloring (Eq. 10-11): F0_i = sum_k rho_k phi_i^k is rho_R alpha_R +
         // rho_B alpha_B at rest, p/6 on the axes and p/12 on the diagonals
+        // rho_R/rho as a correctly rounded quotient: exactly 1 in a pure red
+        // node, so that f^B = f* - f^R keeps pure phases free of the other colour
         const float ir = M.inv_rho;
-        const float ar = s.rR * ir;
+        const float ar = s.rR / rho;
         const float bseg = C.beta * s.rR * s.rB * ir * ir;
         const float sa = bseg * p * (1.0f / 6.0f);
         const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
