@@ -77,6 +77,29 @@ def run_form(B, cases, storage, steps, warmup, timing=True):
         s.close()
 
 
+def copy_probe(mib):
+    """Attainable HBM rate: a plain device-to-device copy of `mib` MiB (read +
+    write counted), timed with HIP events."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 10
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return {"bytes": 2 * mib * (1 << 20), "avg_ms": ms, "GBps": 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(p, fl, budget_s):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (the full 128^3 lattice for a few steps)."""
@@ -103,6 +126,8 @@ def main():
     ap.add_argument("--forms", default="fp16s,bf16s", help="extra storage forms to time ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=1024,
+                    help="size of the device copy that measures the attainable HBM rate (0: skip)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -140,6 +165,8 @@ def main():
                      "max_abs_diff_vs_fp32_after_steps": {"rhoN": err_n, "u": err_u,
                                                           "steps": args.steps + args.warmup}}
 
+    copy = copy_probe(args.copy_probe_mib) if args.copy_probe_mib > 0 else None
+
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -155,6 +182,9 @@ def main():
                      "traffic": traffic},
         "forms": forms,
     }
+    if copy:
+        out["copy_probe"] = copy
+        out["roofline"]["frac_of_copy_probe"] = ach / copy["GBps"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, fl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
