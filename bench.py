@@ -23,13 +23,14 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS + HBM GB/s (% peak): FP32 plain vs FP16-store/surrogate at stated error"
 HBM_PEAK_GBPS = 8000.0
 # Algorithmic HBM bytes per node of one launch of the collision pass: read 38
-# populations, read the node's aux value (rho^N, Qbar), write 38 populations.
-# Shifted 16-bit storage adds the writers' (rho_R, rho_B) read and the node's
-# own (rho_R, rho_B) write.
-COLLIDE_BYTES = {"fp32": 38 * 4 + 16 + 38 * 4, "fp16s": 38 * 2 + 16 + 8 + 38 * 2 + 8,
-                 "bf16s": 38 * 2 + 16 + 8 + 38 * 2 + 8}
-# The method's own minimum per node and step: 38 populations read + written.
-STEP_BYTES = {"fp32": 304, "fp16s": 152, "bf16s": 152}
+# population deviations and the writers' stored (rho_R, rho_B) (8 B per node),
+# read the node's aux value (rho^N, Qbar: 16 B), write 38 deviations and the
+# node's (rho_R, rho_B).
+POP = {"fp32": 4, "fp16s": 2, "bf16s": 2}
+COLLIDE_BYTES = {k: 38 * b + 8 + 16 + 38 * b + 8 for k, b in POP.items()}
+# The method's own minimum per node and step in this storage: populations and
+# stored densities read and written once.
+STEP_BYTES = {k: 2 * (38 * b + 8) for k, b in POP.items()}
 
 
 def kernel_source_hash():

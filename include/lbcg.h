@@ -38,11 +38,12 @@ extern "C" {
 #define LBCG_WALL 1          /* halfway bounce-back wall half a link beyond the
                                 first and last node of the axis */
 
-/* Population storage formats.  Arithmetic is always FP32. */
-#define LBCG_FP32 0          /* plain FP32 populations (152 B per node) */
-#define LBCG_FP16S 1         /* FP16 deviations from the local rest state
-                                rho_k phi_i^k, scaled by 2^10 (76 B per node) */
-#define LBCG_BF16S 2         /* BF16 deviations from rho_k phi_i^k (76 B per node) */
+/* Population storage formats.  Every format stores each population as its
+ * deviation from the rest state rho_k phi_i^k of the node that wrote it, next
+ * to that node's FP32 colour densities (8 B per node); arithmetic is FP32. */
+#define LBCG_FP32 0          /* FP32 deviations (152 B per node) */
+#define LBCG_FP16S 1         /* FP16 deviations scaled by 2^10 (76 B per node) */
+#define LBCG_BF16S 2         /* BF16 deviations (76 B per node) */
 
 /*
  * One independent simulation box.  Fluid parameters follow the paper:

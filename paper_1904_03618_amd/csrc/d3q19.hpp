@@ -34,26 +34,26 @@ __host__ __device__ constexpr int ecls(int i) { return i == 0 ? 0 : (i <= 6 ? 1 
 // the direction with e_opp = -e_i (pairs (1,2), (3,4), ... (17,18))
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 == 1 ? i + 1 : i - 1); }
 
-// Population storage.  Shifted formats keep d = (f - rho_k phi_i^k) * scale,
-// rho_k being the density of the node that wrote the value.
+// Population storage.  Every format keeps deviations d = f - rho_k phi_i^k
+// from the rest state of the node that wrote the value (rho_k: that node's
+// colour density, kept per node in FP32), scaled by 2^s for FP16.  The node's
+// own stored density plus the small deviations carries the populations with
+// well beyond FP32 resolution, so rounding does not bias the colour masses.
 template <int ST> struct Storage;
 template <> struct Storage<LBCG_FP32> {
     using T = float;
-    static constexpr bool shifted = false;
-    __device__ static float dec(T v, float, float) { return v; }
-    __device__ static T enc(float f, float, float) { return f; }
+    __device__ static float dec(T v, float) { return v; }
+    __device__ static T enc(float d, float) { return d; }
 };
 template <> struct Storage<LBCG_FP16S> {
     using T = _Float16;
-    static constexpr bool shifted = true;
-    __device__ static float dec(T v, float shift, float inv_scale) { return __builtin_fmaf((float)v, inv_scale, shift); }
-    __device__ static T enc(float f, float shift, float scale) { return (T)((f - shift) * scale); }
+    __device__ static float dec(T v, float inv_scale) { return (float)v * inv_scale; }
+    __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };
 template <> struct Storage<LBCG_BF16S> {
     using T = __bf16;
-    static constexpr bool shifted = true;
-    __device__ static float dec(T v, float shift, float inv_scale) { return __builtin_fmaf((float)v, inv_scale, shift); }
-    __device__ static T enc(float f, float shift, float scale) { return (T)((f - shift) * scale); }
+    __device__ static float dec(T v, float inv_scale) { return (float)v * inv_scale; }
+    __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };
 
 // Per-case constants, derived on the host in FP64 and rounded once to FP32.
@@ -81,8 +81,8 @@ struct StepArgs {
     void *fout;                  // populations at level t+1
     float4 *aux;                 // per node: rho^N, Qbar_x, Qbar_y, Qbar_z (level t)
     float4 *ghost;               // per wall-plane node: same fields one layer beyond the wall
-    const float2 *rho_prev;      // shifted storage: rho_R, rho_B of the writers of fin
-    float2 *rho_cur;             // shifted storage: rho_R, rho_B written with fout
+    const float2 *rho_prev;      // rho_R, rho_B the writers of fin stored with their values
+    float2 *rho_cur;             // rho_R, rho_B stored with fout
     const DevCase *cases;
     const int2 *tiles;           // (case, first node) per tile
     int ntiles;

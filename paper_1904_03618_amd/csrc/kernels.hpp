@@ -12,6 +12,12 @@
 //             collision in moment space (Eq. 41-45, 53 and the body force),
 //             recoloring (Eq. 10-11) and store at the node's own slots: the
 //             next step's pull completes the streaming.
+// All population arithmetic runs on deviations from the local rest state
+// (see Storage): with S_k the density a node stored at the previous level and
+// R_k its new density, the pulled f_i^k = rho_k(src) phi_i^k + d_i^k enter as
+// h_i = sum_k [(rho_k(src) - S_k) phi_i^k + d_i^k], R_k = S_k + sum of the
+// colour's h terms, and g_i = f_i - sum_k R_k phi_i^k; the rest state is
+// isotropic, so its moments are known in closed form and never rounded.
 // The colour gradient at level t needs the level-t densities of all 18
 // neighbours, so the moments pass must finish before the collision pass.
 #pragma once
@@ -76,12 +82,16 @@ __device__ inline void pull_source(const DevCase &C, const Coord &c, int &src, i
 }
 
 struct NodeState {
-    float f[Q];                  // f_i = f_i^R + f_i^B after streaming
-    float rR, rB, jx, jy, jz;
+    float h[Q];                  // sum_k (rho_k(src) - S_k) phi_i^k + d_i^k
+    float R[2];                  // colour densities R_k = fl(S_k + eps_k)
+    float D[2];                  // R_k - S_k (exact)
+    float eta[2];                // eps_k - (R_k - S_k): what R_k could not hold
+    float jx, jy, jz;            // sum_i e_i f_i (the rest state carries none)
 };
 
 template <int ST, int I>
-__device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
+__device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord &c, const float2 own,
+                                NodeState &s, float &eR, float &eB)
 {
     using S = Storage<ST>;
     using T = typename S::T;
@@ -89,42 +99,46 @@ __device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord
     pull_source<I>(C, c, src, dir);
     const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
     const size_t N = (size_t)C.N;
-    const T vR = base[(size_t)dir * N + src];
-    const T vB = base[(size_t)(Q + dir) * N + src];
-    float shR = 0.f, shB = 0.f;
-    if constexpr (S::shifted) {
-        const float2 rp = a.rho_prev[C.node_off + src];
-        shR = rp.x * C.phi[0][ecls(I)];
-        shB = rp.y * C.phi[1][ecls(I)];
-    }
-    const float fR = S::dec(vR, shR, a.inv_scale);
-    const float fB = S::dec(vB, shB, a.inv_scale);
-    const float ft = fR + fB;
-    s.f[I] = ft;
-    s.rR += fR;
-    s.rB += fB;
-    if constexpr (ex(I) == 1) s.jx += ft;
-    if constexpr (ex(I) == -1) s.jx -= ft;
-    if constexpr (ey(I) == 1) s.jy += ft;
-    if constexpr (ey(I) == -1) s.jy -= ft;
-    if constexpr (ez(I) == 1) s.jz += ft;
-    if constexpr (ez(I) == -1) s.jz -= ft;
+    const float dR = S::dec(base[(size_t)dir * N + src], a.inv_scale);
+    const float dB = S::dec(base[(size_t)(Q + dir) * N + src], a.inv_scale);
+    const float2 ps = a.rho_prev[C.node_off + src];
+    const float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
+    const float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
+    const float h = tR + tB;
+    s.h[I] = h;
+    eR += tR;
+    eB += tB;
+    if constexpr (ex(I) == 1) s.jx += h;
+    if constexpr (ex(I) == -1) s.jx -= h;
+    if constexpr (ey(I) == 1) s.jy += h;
+    if constexpr (ey(I) == -1) s.jy -= h;
+    if constexpr (ez(I) == 1) s.jz += h;
+    if constexpr (ez(I) == -1) s.jz -= h;
 }
 
 template <int ST, int I = 0>
-__device__ inline void pull_all(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
+__device__ inline void pull_all(const StepArgs &a, const DevCase &C, const Coord &c, const float2 own,
+                                NodeState &s, float &eR, float &eB)
 {
     if constexpr (I < Q) {
-        pull_one<ST, I>(a, C, c, s);
-        pull_all<ST, I + 1>(a, C, c, s);
+        pull_one<ST, I>(a, C, c, own, s, eR, eB);
+        pull_all<ST, I + 1>(a, C, c, own, s, eR, eB);
     }
 }
 
 template <int ST>
 __device__ inline void pull_node(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
 {
-    s.rR = s.rB = s.jx = s.jy = s.jz = 0.f;
-    pull_all<ST>(a, C, c, s);
+    const float2 own = a.rho_prev[C.node_off + c.node];
+    float eR = 0.f, eB = 0.f;
+    s.jx = s.jy = s.jz = 0.f;
+    pull_all<ST>(a, C, c, own, s, eR, eB);
+    s.R[0] = own.x + eR;
+    s.R[1] = own.y + eB;
+    s.D[0] = s.R[0] - own.x;
+    s.D[1] = s.R[1] - own.y;
+    s.eta[0] = eR - s.D[0];
+    s.eta[1] = eB - s.D[1];
 }
 
 // Force density (reading: uniform part plus buoyancy) and u = (j + F/2)/rho.
@@ -133,7 +147,7 @@ struct Macro { float rho, inv_rho, Fx, Fy, Fz, ux, uy, uz; };
 __device__ inline Macro macro(const DevCase &C, const NodeState &s)
 {
     Macro m;
-    m.rho = s.rR + s.rB;
+    m.rho = s.R[0] + s.R[1];
     m.inv_rho = 1.0f / m.rho;
     const float dr = m.rho - C.rho_ref;
     m.Fx = C.F[0] + dr * C.g[0];
@@ -165,8 +179,8 @@ __global__ __launch_bounds__(256) void k_aux(StepArgs a)
         NodeState s;
         pull_node<ST>(a, C, c, s);
         const Macro m = macro(C, s);
-        const float qs = s.rR * C.qc[0] + s.rB * C.qc[1];
-        a.aux[C.node_off + node] = make_float4(phase_field(C, s.rR, s.rB), m.ux * qs, m.uy * qs, m.uz * qs);
+        const float qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
+        a.aux[C.node_off + node] = make_float4(phase_field(C, s.R[0], s.R[1]), m.ux * qs, m.uy * qs, m.uz * qs);
     }
 }
 
@@ -278,8 +292,18 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         const float tv = tau_v(C, rn);
         const float sv = 1.0f / tv, se = C.s_e, sq = C.s_q, sp = C.s_pi;
 
-        const float *f = s.f;
-        // raw moments m = M f (Eq. 43, Appendix), rows 4-18
+        // g_i = f_i - sum_k R_k phi_i^k, per velocity class
+        const float dc0 = s.D[0] * C.phi[0][0] + s.D[1] * C.phi[1][0];
+        const float dc1 = s.D[0] * C.phi[0][1] + s.D[1] * C.phi[1][1];
+        const float dc2 = s.D[0] * C.phi[0][2] + s.D[1] * C.phi[1][2];
+        float f[Q];
+        f[0] = s.h[0] - dc0;
+        #pragma unroll
+        for (int i = 1; i < 7; ++i) f[i] = s.h[i] - dc1;
+        #pragma unroll
+        for (int i = 7; i < Q; ++i) f[i] = s.h[i] - dc2;
+        // raw moments M g (Eq. 43, Appendix), rows 4-18; the rest state adds
+        // 3p_R to row 4 and p_R/3 to rows 16-18 (p_R = sum_k R_k (c_s^k)^2)
         const float d78 = f[7] + f[8], d910 = f[9] + f[10];
         const float d1112 = f[11] + f[12], d1314 = f[13] + f[14];
         const float d1516 = f[15] + f[16], d1718 = f[17] + f[18];
@@ -297,16 +321,17 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         const float m15 = f[15] - f[16] + f[17] - f[18];
 
         // two-colour equilibria sum_k m^{k,eq} (Appendix rows 0-15; rows
-        // 16-18 as M f^eq), p = sum_k rho_k (c_s^k)^2
-        const float p = s.rR * C.cs2[0] + s.rB * C.cs2[1];
+        // 16-18 as M f^eq) minus the rest-state moments; p = sum_k rho_k (c_s^k)^2
+        const float p = s.R[0] * C.cs2[0] + s.R[1] * C.cs2[1];
+        const float pe = s.eta[0] * C.cs2[0] + s.eta[1] * C.cs2[1];
         const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
-        const float e4 = 3.0f * p + rho * uu;
+        const float e4 = 3.0f * pe + rho * uu;
         const float e5 = rho * (2.0f * uxx - uyy - uzz);
         const float e6 = rho * (uyy - uzz);
         const float e7 = rho * ux * uy, e8 = rho * ux * uz, e9 = rho * uy * uz;
         const float p3 = C.improved ? p : rho * (1.0f / 3.0f);
         const float e10 = p3 * uy, e11 = p3 * ux, e12 = p3 * uz;
-        const float e16b = (2.0f * p - rho * uu) * (1.0f / 6.0f);
+        const float e16b = (2.0f * pe - rho * uu) * (1.0f / 6.0f);
         const float e16 = e16b + 0.5f * rho * (uxx + uyy);
         const float e17 = e16b + 0.5f * rho * (uxx + uzz);
         const float e18 = e16b + 0.5f * rho * (uyy + uzz);
@@ -364,7 +389,7 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         const float b17 = -sp * (m17 - e17) + hp * f17 + sp * o17;
         const float b18 = -sp * (m18 - e18) + hp * f18 + sp * o18;
 
-        // f* = f + M^-1 mbar (sparse closed form of M^-1)
+        // t = g + M^-1 mbar = f* - sum_k R_k phi^k (sparse closed form of M^-1)
         float fs[Q];
         const float q4 = b4 * (1.0f / 6.0f);
         fs[0] = f[0] - b4 + b16 + b17 + b18;
@@ -400,14 +425,23 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         fs[18] = f[18] + 0.25f * (-b9 + b14 - b15 + b18);
 
         // recoloring (Eq. 10-11): F0_i = sum_k rho_k phi_i^k is rho_R alpha_R +
-        // rho_B alpha_B at rest, p/6 on the axes and p/12 on the diagonals
-        // rho_R/rho as a correctly rounded quotient: exactly 1 in a pure red
-        // node, so that f^B = f* - f^R keeps pure phases free of the other colour
+        // rho_B alpha_B at rest, p/6 on the axes and p/12 on the diagonals.
+        // Stored red deviation: rho_R/rho f*_i + seg_i - R_R phi_i^R
+        //   = (rho_R/rho) t_i + seg_i + cr_i,
+        // cr_i = [R_R R_B (phi_i^B - phi_i^R) + eta_R R_B phi_i^B - eta_B R_R phi_i^R]/rho;
+        // blue: t_i - (red deviation).  rho_R/rho is a correctly rounded
+        // quotient (exactly 1 in a pure red node, so pure phases stay pure).
         const float ir = M.inv_rho;
-        const float ar = s.rR / rho;
-        const float bseg = C.beta * s.rR * s.rB * ir * ir;
+        const float RR = s.R[0], RB = s.R[1];
+        const float ar = RR / rho;
+        const float bseg = C.beta * RR * RB * ir * ir;
         const float sa = bseg * p * (1.0f / 6.0f);
         const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
+        const float rr = RR * RB;
+        float cr[3];
+        #pragma unroll
+        for (int k = 0; k < 3; ++k)
+            cr[k] = (rr * (C.phi[1][k] - C.phi[0][k]) + s.eta[0] * RB * C.phi[1][k] - s.eta[1] * RR * C.phi[0][k]) * ir;
         float seg[Q];
         seg[0] = 0.f;
         seg[1] = sa * nx; seg[2] = -sa * nx; seg[3] = sa * ny; seg[4] = -sa * ny;
@@ -420,17 +454,12 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         const size_t N = (size_t)C.N;
         #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const float fr = ar * fs[i] + seg[i];
-            const float fb = fs[i] - fr;
-            float shR = 0.f, shB = 0.f;
-            if constexpr (S::shifted) {
-                shR = s.rR * C.phi[0][ecls(i)];
-                shB = s.rB * C.phi[1][ecls(i)];
-            }
-            outb[(size_t)i * N + node] = S::enc(fr, shR, a.scale);
-            outb[(size_t)(Q + i) * N + node] = S::enc(fb, shB, a.scale);
+            const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
+            const float db = fs[i] - dr;
+            outb[(size_t)i * N + node] = S::enc(dr, a.scale);
+            outb[(size_t)(Q + i) * N + node] = S::enc(db, a.scale);
         }
-        if constexpr (S::shifted) a.rho_cur[C.node_off + node] = make_float2(s.rR, s.rB);
+        a.rho_cur[C.node_off + node] = make_float2(RR, RB);
     }
 }
 
@@ -451,16 +480,17 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, int tile0, float *r
         NodeState s;
         pull_node<ST>(a, C, c, s);
         const Macro m = macro(C, s);
-        if (rR) rR[node] = s.rR;
-        if (rB) rB[node] = s.rB;
-        if (rN) rN[node] = phase_field(C, s.rR, s.rB);
+        if (rR) rR[node] = s.R[0];
+        if (rB) rB[node] = s.R[1];
+        if (rN) rN[node] = phase_field(C, s.R[0], s.R[1]);
         if (ux) ux[node] = m.ux;
         if (uy) uy[node] = m.uy;
         if (uz) uz[node] = m.uz;
-        v[0] = s.rR; v[1] = s.rB;
+        v[0] = (double)s.R[0] + (double)s.eta[0];
+        v[1] = (double)s.R[1] + (double)s.eta[1];
         v[2] = (double)m.rho * m.ux; v[3] = (double)m.rho * m.uy; v[4] = (double)m.rho * m.uz;
-        const bool bad = !(isfinite(s.rR) && isfinite(s.rB) && isfinite(m.ux) && isfinite(m.uy) &&
-                           isfinite(m.uz)) || s.rR < C.neg_tol[0] || s.rB < C.neg_tol[1];
+        const bool bad = !(isfinite(s.R[0]) && isfinite(s.R[1]) && isfinite(m.ux) && isfinite(m.uy) &&
+                           isfinite(m.uz)) || s.R[0] < C.neg_tol[0] || s.R[1] < C.neg_tol[1];
         v[5] = bad ? 1.0 : 0.0;
     }
     // wavefront reduction (64 lanes), then across the 4 wavefronts
@@ -534,11 +564,10 @@ __device__ inline void get_dirs(const StepArgs &a, const DevCase &C, const Coord
         pull_source<I>(C, c, src, dir);
         const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
         const size_t N = (size_t)C.N;
-        float2 rp = make_float2(0.f, 0.f);
-        if constexpr (S::shifted) rp = a.rho_prev[C.node_off + src];
-        out[(size_t)I * N + c.node] = S::dec(base[(size_t)dir * N + src], rp.x * C.phi[0][ecls(I)], a.inv_scale);
+        const float2 rp = a.rho_prev[C.node_off + src];
+        out[(size_t)I * N + c.node] = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(base[(size_t)dir * N + src], a.inv_scale));
         out[(size_t)(Q + I) * N + c.node] =
-            S::dec(base[(size_t)(Q + dir) * N + src], rp.y * C.phi[1][ecls(I)], a.inv_scale);
+            __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(base[(size_t)(Q + dir) * N + src], a.inv_scale));
         get_dirs<ST, I + 1>(a, C, c, out);
     }
 }
@@ -556,7 +585,7 @@ __global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out
 // FP64 and rounded once into the storage format.  The buffers hold values that
 // the next pull reads, so f_i^{k,eq}(y) is stored in the slot the pull of
 // (y, i) reads: (src, dir) of pull_source, which is a permutation of all
-// slots.  A shifted slot at src is encoded relative to rho_k(src) phi_i^k.
+// slots.  The slot at src holds the deviation from rho_k(src) phi_i^k.
 struct InitCase { double alpha[2]; int improved; };
 
 template <int ST, int I = 0>
@@ -582,14 +611,9 @@ __device__ inline void init_dirs(const StepArgs &a, const DevCase &C, const Coor
             double br = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
             if (ic.improved) br += 3.0 * eu * (3.0 * cs2 - 1.0) * (3.0 * cl - 5.0);
             const double fe = r[k] * (ph + w * br);
-            T v;
-            if constexpr (S::shifted) {
-                const float rs = (float)(k == 0 ? rR0[src] : rB0[src]);
-                v = (T)((fe - (double)(rs * C.phi[k][cl])) * (double)a.scale);
-            } else {
-                v = (T)fe;
-            }
-            base[(size_t)(k * Q + dir) * N + src] = v;
+            const float rs = (float)(k == 0 ? rR0[src] : rB0[src]);
+            const double dev = fe - (double)rs * (double)C.phi[k][cl];
+            base[(size_t)(k * Q + dir) * N + src] = (T)(float)(dev * (double)a.scale);
         }
         init_dirs<ST, I + 1>(a, C, c, ic, r, u, uu, rR0, rB0);
     }
@@ -607,7 +631,7 @@ __global__ __launch_bounds__(256) void k_init(StepArgs a, int cid, InitCase ic, 
     const double u[3] = {ux0[node], uy0[node], uz0[node]};
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     init_dirs<ST>(a, C, make_coord(C, node), ic, r, u, uu, rR0, rB0);
-    if constexpr (Storage<ST>::shifted) a.rho_cur[C.node_off + node] = make_float2((float)r[0], (float)r[1]);
+    a.rho_cur[C.node_off + node] = make_float2((float)r[0], (float)r[1]);
 }
 
 }  // namespace lbcg

@@ -387,7 +387,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
               alloc((void **)&h->ghost, sizeof(float4) * std::max<int64_t>(1, h->total_ghost)) &&
               alloc((void **)&h->partial, sizeof(double) * 6 * (size_t)h->ntiles) &&
               alloc((void **)&h->red, sizeof(double) * 8);
-    if (ok && h->storage != LBCG_FP32)
+    if (ok)
         ok = alloc((void **)&h->rho2[0], sizeof(float2) * h->total_nodes) &&
              alloc((void **)&h->rho2[1], sizeof(float2) * h->total_nodes);
     if (!ok) {

@@ -139,6 +139,17 @@ def test_lattice_centred_droplet(maker):
         assert e[k] <= 10 * env[k] + 1e-6, (k, e[k], env[k])
 
 
+@pytest.mark.parametrize("storage,tn,tu", [("fp16s", 2e-3, 2e-5), ("bf16s", 2e-2, 2e-4)])
+@pytest.mark.parametrize("name", ["paper_fluids_32_offcentre", "galilean_24", "walls_wetting_force"])
+def test_shifted_storage_500_steps(storage, tn, tu, name):
+    """16-bit deviation storage (FP32 arithmetic) against the FP64 oracle after
+    500 steps; the bounds are the stated errors of these forms."""
+    p, fl = _cases()[name]()
+    g = gpu_run([(p, fl)], 500, storage=storage)[0]
+    o = oracle_run(p, fl, 500)
+    assert_parity(f"{storage}_{name}", g, o, p, tn=tn, tu=tu, tr=tn)
+
+
 def test_batched_cases_match_single_runs_and_oracle():
     """Uneven boxes with different fluids, walls and contact angles in one
     handle (one persistent launch per kernel): each equals its single-case
