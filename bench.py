@@ -28,6 +28,9 @@ HBM_PEAK_GBPS = 8000.0
 # node's (rho_R, rho_B).
 POP = {"fp32": 4, "fp16s": 2, "bf16s": 2}
 COLLIDE_BYTES = {k: 38 * b + 8 + 16 + 38 * b + 8 for k, b in POP.items()}
+# The fused single-pass step: populations and stored densities read and
+# written once (the phase-field halo lives in LDS).
+FUSED_BYTES = {k: 2 * (38 * b + 8) for k, b in POP.items()}
 # The method's own minimum per node and step in this storage: populations and
 # stored densities read and written once.
 STEP_BYTES = {k: 2 * (38 * b + 8) for k, b in POP.items()}
@@ -41,10 +44,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage):
-    """HBM bytes per collision launch from the committed rocprofv3 counter
-    summary, only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_collide_{storage}_galilean128_traffic.json")
+def measured_traffic(storage, kernel):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_galilean128_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -54,9 +57,16 @@ def measured_traffic(storage):
     return d.get("bytes_per_launch")
 
 
-def run_form(B, cases, storage, steps, warmup, timing=True):
+def dominant(kt, storage):
+    """(name, avg ms, algorithmic bytes per node) of the kernel that dominates a step."""
+    if kt["fused"][1]:
+        return "k_fused", kt["fused"][0] / kt["fused"][1], FUSED_BYTES[storage]
+    return "k_collide", kt["collide"][0] / kt["collide"][1], COLLIDE_BYTES[storage]
+
+
+def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto"):
     import torch
-    s = B.Solver(cases, storage=storage)
+    s = B.Solver(cases, storage=storage, kernel=kernel)
     try:
         s.step(warmup)
         torch.cuda.synchronize()
@@ -126,6 +136,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--forms", default="fp16s,bf16s", help="extra storage forms to time ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the device copy that measures the attainable HBM rate (0: skip)")
@@ -145,24 +156,22 @@ def main():
     N = p["nx"] * p["ny"] * p["nz"]
     cases = [(p, fl)]
 
-    ms, kt, ref = run_form(B, cases, "fp32", args.steps, args.warmup)
+    ms, kt, ref = run_form(B, cases, "fp32", args.steps, args.warmup, kernel=args.kernel)
     ms_step = ms / args.steps
     mlups = N * args.steps / (ms * 1e-3) / 1e6
-    col_ms, col_n = kt["collide"]
-    aux_ms, aux_n = kt["aux"]
-    avg_col = col_ms / col_n
-    ach = COLLIDE_BYTES["fp32"] * N / (avg_col * 1e-3) / 1e9
-    traffic = measured_traffic("fp32")
+    kname, avg_col, kbytes = dominant(kt, "fp32")
+    ach = kbytes * N / (avg_col * 1e-3) / 1e9
+    traffic = measured_traffic("fp32", kname)
 
     forms = {}
     for st in [s for s in args.forms.split(",") if s]:
-        fms, fkt, ff = run_form(B, cases, st, args.steps, args.warmup)
-        c_ms, c_n = fkt["collide"]
+        fms, fkt, ff = run_form(B, cases, st, args.steps, args.warmup, kernel=args.kernel)
+        fname, f_avg, f_bytes = dominant(fkt, st)
         err_n = float((ff["rhoN"] - ref["rhoN"]).abs().max())
         err_u = float(max((ff[k] - ref[k]).abs().max() for k in ("ux", "uy", "uz")))
         forms[st] = {"MLUPS": N * args.steps / (fms * 1e-3) / 1e6, "ms_per_step": fms / args.steps,
-                     "collide_avg_ms": c_ms / c_n,
-                     "collide_GBps": COLLIDE_BYTES[st] * N / (c_ms / c_n * 1e-3) / 1e9,
+                     "kernel": fname, "kernel_avg_ms": f_avg,
+                     "kernel_GBps": f_bytes * N / (f_avg * 1e-3) / 1e9,
                      "max_abs_diff_vs_fp32_after_steps": {"rhoN": err_n, "u": err_u,
                                                           "steps": args.steps + args.warmup}}
 
@@ -176,11 +185,10 @@ def main():
                    "lattice": [128, 128, 128], "storage": "fp32", "tau_v": p["tau_v"][0],
                    "parallelism": "single GPU"},
         "step_algorithmic_GBps": mlups * 1e6 * STEP_BYTES["fp32"] / 1e9,
-        "kernels_avg_ms": {"aux": aux_ms / aux_n, "collide": avg_col},
+        "kernels_avg_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBPS, "kernel": "k_collide<fp32>",
-                     "bytes_per_node": COLLIDE_BYTES["fp32"],
-                     "traffic": traffic},
+                     "frac": ach / HBM_PEAK_GBPS, "kernel": kname + "<fp32>",
+                     "bytes_per_node": kbytes, "traffic": traffic},
         "forms": forms,
     }
     if copy:

@@ -93,17 +93,27 @@ typedef struct lbcg_fields {
     int32_t reserved;
 } lbcg_fields;
 
+/* Step kernels. */
+#define LBCG_KERNEL_AUTO 0      /* fused when every case is eligible, else two-pass */
+#define LBCG_KERNEL_TWOPASS 1   /* moments pass + collision pass (any boundaries) */
+#define LBCG_KERNEL_FUSED 2     /* single pass, z-marching tiles with an LDS halo;
+                                   eligible cases: walls only on z, and those
+                                   walls neutral (theta = 90 deg) */
+
 /* Handle-wide options.  storage: LBCG_FP32 / LBCG_FP16S / LBCG_BF16S.
  * diag_every: run the stability check every this many steps inside
- * lbcg_step (0 = never).  block_nodes: nodes per work tile and workgroup
- * (0 = default 256; 64, 128, 192 or 256).  persistent_blocks: 0 = one
- * workgroup per tile, >0 = that many workgroups looping over all tiles of all
- * cases (batched persistent launch). */
+ * lbcg_step (0 = never).  block_nodes: nodes per work tile and workgroup of
+ * the two-pass kernels (0 = default 256; 64, 128, 192 or 256).
+ * persistent_blocks: 0 = one workgroup per tile, >0 = that many workgroups
+ * looping over all tiles of all cases (batched persistent launch).
+ * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default 16). */
 typedef struct lbcg_options {
     int32_t storage;
     int32_t diag_every;
     int32_t block_nodes;
     int32_t persistent_blocks;
+    int32_t kernel;
+    int32_t zchunk;
 } lbcg_options;
 
 typedef struct lbcg_handle lbcg_handle;
@@ -170,9 +180,9 @@ int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f);
 /* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
  * recording an event pair around every kernel of every following step
  * (enable = 0 stops).  lbcg_timing_read synchronises the stream and writes,
- * for the kernels {moments/aux pass, wall ghost layer, collision pass}, the
- * summed duration in milliseconds into ms[3] and the number of recorded
- * launches into launches[3]; it then clears the totals.  Errors: LBCG_ESTATE,
+ * for the kernels {moments pass, wall ghost layer, collision pass, fused
+ * step}, the summed duration in milliseconds into ms[4] and the number of
+ * recorded launches into launches[4]; it then clears the totals.  Errors: LBCG_ESTATE,
  * LBCG_EINVAL (NULL output), LBCG_EDEVICE. */
 int lbcg_timing(lbcg_handle *h, int32_t enable);
 int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches);

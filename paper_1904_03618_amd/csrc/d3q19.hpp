@@ -56,6 +56,36 @@ template <> struct Storage<LBCG_BF16S> {
     __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };
 
+// Population streams are touched once per pass: non-temporal accesses keep
+// them from displacing the reused per-node arrays (aux stencil, stored
+// densities) from L2.
+#ifndef LBCG_NT_LOAD
+#define LBCG_NT_LOAD 1
+#endif
+#ifndef LBCG_NT_STORE
+#define LBCG_NT_STORE 1
+#endif
+
+template <class T>
+__device__ inline T ld_stream(const T *p)
+{
+#if LBCG_NT_LOAD
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
+template <class T>
+__device__ inline void st_stream(T *p, T v)
+{
+#if LBCG_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
 // Per-case constants, derived on the host in FP64 and rounded once to FP32.
 struct DevCase {
     int nx, ny, nz, wall;        // wall: -1 none, else the wall axis

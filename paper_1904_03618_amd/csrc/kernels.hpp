@@ -99,8 +99,8 @@ __device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord
     pull_source<I>(C, c, src, dir);
     const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
     const size_t N = (size_t)C.N;
-    const float dR = S::dec(base[(size_t)dir * N + src], a.inv_scale);
-    const float dB = S::dec(base[(size_t)(Q + dir) * N + src], a.inv_scale);
+    const float dR = S::dec(ld_stream(&base[(size_t)dir * N + src]), a.inv_scale);
+    const float dB = S::dec(ld_stream(&base[(size_t)(Q + dir) * N + src]), a.inv_scale);
     const float2 ps = a.rho_prev[C.node_off + src];
     const float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
     const float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
@@ -268,12 +268,197 @@ __device__ inline float tau_v(const DevCase &C, float rn)
     return C.s1 + rn * (C.t2 + rn * C.t3);
 }
 
+// ------------------------------------------------------------- collision
+// One node: tau_v (Eq. 52), the two-colour MRT collision in moment space with
+// correction term, body force and perturbation (Eq. 41-45, 53), recoloring
+// (Eq. 10-11) and the store of both colours' deviations at the node's own
+// slots.  st: colour gradient and Q_alpha (Eq. 49); rn: the node's rho^N.
+template <int ST>
+__device__ inline void collide_node(const StepArgs &a, const DevCase &C, int node, const NodeState &s,
+                                    const Stencil &st, float rn)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    const Macro M = macro(C, s);
+    const float ux = M.ux, uy = M.uy, uz = M.uz, rho = M.rho;
+
+    const float tv = tau_v(C, rn);
+    const float sv = 1.0f / tv, se = C.s_e, sq = C.s_q, sp = C.s_pi;
+
+    // g_i = f_i - sum_k R_k phi_i^k, per velocity class
+    const float dc0 = s.D[0] * C.phi[0][0] + s.D[1] * C.phi[1][0];
+    const float dc1 = s.D[0] * C.phi[0][1] + s.D[1] * C.phi[1][1];
+    const float dc2 = s.D[0] * C.phi[0][2] + s.D[1] * C.phi[1][2];
+    float f[Q];
+    f[0] = s.h[0] - dc0;
+    #pragma unroll
+    for (int i = 1; i < 7; ++i) f[i] = s.h[i] - dc1;
+    #pragma unroll
+    for (int i = 7; i < Q; ++i) f[i] = s.h[i] - dc2;
+    // raw moments M g (Eq. 43, Appendix), rows 4-18; the rest state adds
+    // 3p_R to row 4 and p_R/3 to rows 16-18 (p_R = sum_k R_k (c_s^k)^2)
+    const float d78 = f[7] + f[8], d910 = f[9] + f[10];
+    const float d1112 = f[11] + f[12], d1314 = f[13] + f[14];
+    const float d1516 = f[15] + f[16], d1718 = f[17] + f[18];
+    const float a12 = f[1] + f[2], a34 = f[3] + f[4], a56 = f[5] + f[6];
+    const float m16 = d78 + d910, m17 = d1112 + d1314, m18 = d1516 + d1718;
+    const float m4 = a12 + a34 + a56 + 2.0f * (m16 + m17 + m18);
+    const float m5 = 2.0f * a12 - a34 - a56 + m16 + m17 - 2.0f * m18;
+    const float m6 = a34 - a56 + m16 - m17;
+    const float m7 = d78 - d910, m8 = d1112 - d1314, m9 = d1516 - d1718;
+    const float m10 = f[7] - f[8] - f[9] + f[10];
+    const float m11 = f[7] - f[8] + f[9] - f[10];
+    const float m12 = f[11] - f[12] - f[13] + f[14];
+    const float m13 = f[11] - f[12] + f[13] - f[14];
+    const float m14 = f[15] - f[16] - f[17] + f[18];
+    const float m15 = f[15] - f[16] + f[17] - f[18];
+
+    // two-colour equilibria sum_k m^{k,eq} (Appendix rows 0-15; rows
+    // 16-18 as M f^eq) minus the rest-state moments; p = sum_k rho_k (c_s^k)^2
+    const float p = s.R[0] * C.cs2[0] + s.R[1] * C.cs2[1];
+    const float pe = s.eta[0] * C.cs2[0] + s.eta[1] * C.cs2[1];
+    const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
+    const float e4 = 3.0f * pe + rho * uu;
+    const float e5 = rho * (2.0f * uxx - uyy - uzz);
+    const float e6 = rho * (uyy - uzz);
+    const float e7 = rho * ux * uy, e8 = rho * ux * uz, e9 = rho * uy * uz;
+    const float p3 = C.improved ? p : rho * (1.0f / 3.0f);
+    const float e10 = p3 * uy, e11 = p3 * ux, e12 = p3 * uz;
+    const float e16b = (2.0f * pe - rho * uu) * (1.0f / 6.0f);
+    const float e16 = e16b + 0.5f * rho * (uxx + uyy);
+    const float e17 = e16b + 0.5f * rho * (uxx + uzz);
+    const float e18 = e16b + 0.5f * rho * (uyy + uzz);
+
+    // correction term (Eq. 45), summed over the colours
+    float c4 = 0.f, c5 = 0.f, c6 = 0.f;
+    if (C.improved) {
+        c4 = st.Qx + st.Qy + st.Qz;
+        c5 = 2.0f * st.Qx - st.Qy - st.Qz;
+        c6 = st.Qy - st.Qz;
+    }
+    // body force in moment space (reading: Guo's source, M F^Guo)
+    const float Fx = M.Fx, Fy = M.Fy, Fz = M.Fz;
+    const float uFx = ux * Fx, uFy = uy * Fy, uFz = uz * Fz;
+    const float f4 = 2.0f * (uFx + uFy + uFz);
+    const float f5 = 2.0f * (2.0f * uFx - uFy - uFz);
+    const float f6 = 2.0f * (uFy - uFz);
+    const float f7 = ux * Fy + uy * Fx, f8 = ux * Fz + uz * Fx, f9 = uy * Fz + uz * Fy;
+    const float t3 = 1.0f / 3.0f;
+    const float f16 = (2.0f * uFx + 2.0f * uFy - uFz) * t3;
+    const float f17 = (2.0f * uFx - uFy + 2.0f * uFz) * t3;
+    const float f18 = (-uFx + 2.0f * uFy + 2.0f * uFz) * t3;
+    // perturbation in moment space: M Omega2 summed over the colours
+    // (Eq. 8), relaxed by S (Eq. 53)
+    const float g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
+    float o4 = 0.f, o5 = 0.f, o6 = 0.f, o7 = 0.f, o8 = 0.f, o9 = 0.f, o16 = 0.f, o17 = 0.f, o18 = 0.f;
+    float nx = 0.f, ny = 0.f, nz = 0.f;
+    if (g2 > 1e-24f) {
+        const float ig = rsqrtf(g2);
+        nx = st.gx * ig; ny = st.gy * ig; nz = st.gz * ig;
+        const float ag = C.Asum * ig * (1.0f / 9.0f);
+        const float gxx = st.gx * st.gx, gyy = st.gy * st.gy, gzz = st.gz * st.gz;
+        o4 = -2.0f * ag * g2;
+        o5 = ag * (3.0f * gxx - g2);
+        o6 = ag * (gyy - gzz);
+        o7 = ag * st.gx * st.gy; o8 = ag * st.gx * st.gz; o9 = ag * st.gy * st.gz;
+        o16 = -0.5f * ag * gzz; o17 = -0.5f * ag * gyy; o18 = -0.5f * ag * gxx;
+    }
+    // post-collision moment changes mbar (Eq. 41 + force + Eq. 53); rows
+    // 0-3: mass unchanged, momentum changed by F (exact for the sum)
+    const float he = 1.0f - 0.5f * se, hv = 1.0f - 0.5f * sv, hq = 1.0f - 0.5f * sq, hp = 1.0f - 0.5f * sp;
+    const float b4 = -se * (m4 - e4) + he * (c4 + f4) + se * o4;
+    const float b5 = -sv * (m5 - e5) + hv * (c5 + f5) + sv * o5;
+    const float b6 = -sv * (m6 - e6) + hv * (c6 + f6) + sv * o6;
+    const float b7 = -sv * (m7 - e7) + hv * f7 + sv * o7;
+    const float b8 = -sv * (m8 - e8) + hv * f8 + sv * o8;
+    const float b9 = -sv * (m9 - e9) + hv * f9 + sv * o9;
+    const float b10 = -sq * (m10 - e10) + hq * (Fy * t3);
+    const float b11 = -sq * (m11 - e11) + hq * (Fx * t3);
+    const float b12 = -sq * (m12 - e12) + hq * (Fz * t3);
+    const float b13 = -sq * (m13 - e11) + hq * (Fx * t3);
+    const float b14 = -sq * (m14 - e12) + hq * (Fz * t3);
+    const float b15 = -sq * (m15 - e10) + hq * (Fy * t3);
+    const float b16 = -sp * (m16 - e16) + hp * f16 + sp * o16;
+    const float b17 = -sp * (m17 - e17) + hp * f17 + sp * o17;
+    const float b18 = -sp * (m18 - e18) + hp * f18 + sp * o18;
+
+    // t = g + M^-1 mbar = f* - sum_k R_k phi^k (sparse closed form of M^-1)
+    float fs[Q];
+    const float q4 = b4 * (1.0f / 6.0f);
+    fs[0] = f[0] - b4 + b16 + b17 + b18;
+    {
+        const float base = q4 + b5 * (1.0f / 6.0f) - 0.5f * (b16 + b17);
+        const float odd = 0.5f * (Fx - b11 - b13);
+        fs[1] = f[1] + base + odd;
+        fs[2] = f[2] + base - odd;
+    }
+    {
+        const float base = q4 - b5 * (1.0f / 12.0f) + 0.25f * b6 - 0.5f * (b16 + b18);
+        const float odd = 0.5f * (Fy - b10 - b15);
+        fs[3] = f[3] + base + odd;
+        fs[4] = f[4] + base - odd;
+    }
+    {
+        const float base = q4 - b5 * (1.0f / 12.0f) - 0.25f * b6 - 0.5f * (b17 + b18);
+        const float odd = 0.5f * (Fz - b12 - b14);
+        fs[5] = f[5] + base + odd;
+        fs[6] = f[6] + base - odd;
+    }
+    fs[7] = f[7] + 0.25f * (b7 + b10 + b11 + b16);
+    fs[8] = f[8] + 0.25f * (b7 - b10 - b11 + b16);
+    fs[9] = f[9] + 0.25f * (-b7 - b10 + b11 + b16);
+    fs[10] = f[10] + 0.25f * (-b7 + b10 - b11 + b16);
+    fs[11] = f[11] + 0.25f * (b8 + b12 + b13 + b17);
+    fs[12] = f[12] + 0.25f * (b8 - b12 - b13 + b17);
+    fs[13] = f[13] + 0.25f * (-b8 - b12 + b13 + b17);
+    fs[14] = f[14] + 0.25f * (-b8 + b12 - b13 + b17);
+    fs[15] = f[15] + 0.25f * (b9 + b14 + b15 + b18);
+    fs[16] = f[16] + 0.25f * (b9 - b14 - b15 + b18);
+    fs[17] = f[17] + 0.25f * (-b9 - b14 + b15 + b18);
+    fs[18] = f[18] + 0.25f * (-b9 + b14 - b15 + b18);
+
+    // recoloring (Eq. 10-11): F0_i = sum_k rho_k phi_i^k is rho_R alpha_R +
+    // rho_B alpha_B at rest, p/6 on the axes and p/12 on the diagonals.
+    // Stored red deviation: rho_R/rho f*_i + seg_i - R_R phi_i^R
+    //   = (rho_R/rho) t_i + seg_i + cr_i,
+    // cr_i = [R_R R_B (phi_i^B - phi_i^R) + eta_R R_B phi_i^B - eta_B R_R phi_i^R]/rho;
+    // blue: t_i - (red deviation).  rho_R/rho is a correctly rounded
+    // quotient (exactly 1 in a pure red node, so pure phases stay pure).
+    const float ir = M.inv_rho;
+    const float RR = s.R[0], RB = s.R[1];
+    const float ar = RR / rho;
+    const float bseg = C.beta * RR * RB * ir * ir;
+    const float sa = bseg * p * (1.0f / 6.0f);
+    const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
+    const float rr = RR * RB;
+    float cr[3];
+    #pragma unroll
+    for (int k = 0; k < 3; ++k)
+        cr[k] = (rr * (C.phi[1][k] - C.phi[0][k]) + s.eta[0] * RB * C.phi[1][k] - s.eta[1] * RR * C.phi[0][k]) * ir;
+    float seg[Q];
+    seg[0] = 0.f;
+    seg[1] = sa * nx; seg[2] = -sa * nx; seg[3] = sa * ny; seg[4] = -sa * ny;
+    seg[5] = sa * nz; seg[6] = -sa * nz;
+    seg[7] = sd * (nx + ny); seg[8] = -seg[7]; seg[9] = sd * (nx - ny); seg[10] = -seg[9];
+    seg[11] = sd * (nx + nz); seg[12] = -seg[11]; seg[13] = sd * (nx - nz); seg[14] = -seg[13];
+    seg[15] = sd * (ny + nz); seg[16] = -seg[15]; seg[17] = sd * (ny - nz); seg[18] = -seg[17];
+
+    T *outb = reinterpret_cast<T *>(a.fout) + C.pop_off;
+    const size_t N = (size_t)C.N;
+    #pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
+        const float db = fs[i] - dr;
+        st_stream(&outb[(size_t)i * N + node], S::enc(dr, a.scale));
+        st_stream(&outb[(size_t)(Q + i) * N + node], S::enc(db, a.scale));
+    }
+    a.rho_cur[C.node_off + node] = make_float2(RR, RB);
+}
+
 // ------------------------------------------------------------- k_collide
 template <int ST>
 __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 {
-    using S = Storage<ST>;
-    using T = typename S::T;
     const TileRange tr = tile_range(a.ntiles);
     for (int t = tr.first; t < tr.end; t += tr.stride) {
         const int2 tl = a.tiles[t];
@@ -283,183 +468,138 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         const Coord c = make_coord(C, node);
         NodeState s;
         pull_node<ST>(a, C, c, s);
-        const Macro M = macro(C, s);
-        const float ux = M.ux, uy = M.uy, uz = M.uz, rho = M.rho;
-
         Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         stencil_acc(a, C, c, st);
-        const float rn = a.aux[C.node_off + node].x;
-        const float tv = tau_v(C, rn);
-        const float sv = 1.0f / tv, se = C.s_e, sq = C.s_q, sp = C.s_pi;
+        collide_node<ST>(a, C, node, s, st, a.aux[C.node_off + node].x);
+    }
+}
 
-        // g_i = f_i - sum_k R_k phi_i^k, per velocity class
-        const float dc0 = s.D[0] * C.phi[0][0] + s.D[1] * C.phi[1][0];
-        const float dc1 = s.D[0] * C.phi[0][1] + s.D[1] * C.phi[1][1];
-        const float dc2 = s.D[0] * C.phi[0][2] + s.D[1] * C.phi[1][2];
-        float f[Q];
-        f[0] = s.h[0] - dc0;
-        #pragma unroll
-        for (int i = 1; i < 7; ++i) f[i] = s.h[i] - dc1;
-        #pragma unroll
-        for (int i = 7; i < Q; ++i) f[i] = s.h[i] - dc2;
-        // raw moments M g (Eq. 43, Appendix), rows 4-18; the rest state adds
-        // 3p_R to row 4 and p_R/3 to rows 16-18 (p_R = sum_k R_k (c_s^k)^2)
-        const float d78 = f[7] + f[8], d910 = f[9] + f[10];
-        const float d1112 = f[11] + f[12], d1314 = f[13] + f[14];
-        const float d1516 = f[15] + f[16], d1718 = f[17] + f[18];
-        const float a12 = f[1] + f[2], a34 = f[3] + f[4], a56 = f[5] + f[6];
-        const float m16 = d78 + d910, m17 = d1112 + d1314, m18 = d1516 + d1718;
-        const float m4 = a12 + a34 + a56 + 2.0f * (m16 + m17 + m18);
-        const float m5 = 2.0f * a12 - a34 - a56 + m16 + m17 - 2.0f * m18;
-        const float m6 = a34 - a56 + m16 - m17;
-        const float m7 = d78 - d910, m8 = d1112 - d1314, m9 = d1516 - d1718;
-        const float m10 = f[7] - f[8] - f[9] + f[10];
-        const float m11 = f[7] - f[8] + f[9] - f[10];
-        const float m12 = f[11] - f[12] - f[13] + f[14];
-        const float m13 = f[11] - f[12] + f[13] - f[14];
-        const float m14 = f[15] - f[16] - f[17] + f[18];
-        const float m15 = f[15] - f[16] + f[17] - f[18];
+// ---------------------------------------------------------------- k_fused
+// Single-pass step.  A workgroup owns an FTX x FTY column of nodes over a
+// chunk of z-planes and marches up the chunk.  For each plane it pulls the
+// populations of the tile and of its one-node x-y halo, writes their aux values
+// (rho^N, Qbar) into a three-plane LDS ring, and then collides the plane below
+// from registers with the colour-gradient and correction stencils read from
+// LDS.  Populations are read once per plane plus the halo ring and the two
+// extra planes of each chunk; aux never goes to HBM.  Eligible cases: walls
+// (if any) on z with neutral wetting (cot theta = 0), where the ghost layer is
+// the mirror of the first layer with Qbar reflected oddly.
+constexpr int FTX = 16, FTY = 16;
+constexpr int FRX = FTX + 2, FRY = FTY + 2, FREG = FRX * FRY;
 
-        // two-colour equilibria sum_k m^{k,eq} (Appendix rows 0-15; rows
-        // 16-18 as M f^eq) minus the rest-state moments; p = sum_k rho_k (c_s^k)^2
-        const float p = s.R[0] * C.cs2[0] + s.R[1] * C.cs2[1];
-        const float pe = s.eta[0] * C.cs2[0] + s.eta[1] * C.cs2[1];
-        const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
-        const float e4 = 3.0f * pe + rho * uu;
-        const float e5 = rho * (2.0f * uxx - uyy - uzz);
-        const float e6 = rho * (uyy - uzz);
-        const float e7 = rho * ux * uy, e8 = rho * ux * uz, e9 = rho * uy * uz;
-        const float p3 = C.improved ? p : rho * (1.0f / 3.0f);
-        const float e10 = p3 * uy, e11 = p3 * ux, e12 = p3 * uz;
-        const float e16b = (2.0f * pe - rho * uu) * (1.0f / 6.0f);
-        const float e16 = e16b + 0.5f * rho * (uxx + uyy);
-        const float e17 = e16b + 0.5f * rho * (uxx + uzz);
-        const float e18 = e16b + 0.5f * rho * (uyy + uzz);
+struct FusedArgs {
+    StepArgs a;
+    const int4 *ftiles;          // (case, x0, y0, z0)
+    int nftiles;
+    int zc;                      // planes per chunk
+};
 
-        // correction term (Eq. 45), summed over the colours
-        float c4 = 0.f, c5 = 0.f, c6 = 0.f;
-        if (C.improved) {
-            c4 = st.Qx + st.Qy + st.Qz;
-            c5 = 2.0f * st.Qx - st.Qy - st.Qz;
-            c6 = st.Qy - st.Qz;
-        }
-        // body force in moment space (reading: Guo's source, M F^Guo)
-        const float Fx = M.Fx, Fy = M.Fy, Fz = M.Fz;
-        const float uFx = ux * Fx, uFy = uy * Fy, uFz = uz * Fz;
-        const float f4 = 2.0f * (uFx + uFy + uFz);
-        const float f5 = 2.0f * (2.0f * uFx - uFy - uFz);
-        const float f6 = 2.0f * (uFy - uFz);
-        const float f7 = ux * Fy + uy * Fx, f8 = ux * Fz + uz * Fx, f9 = uy * Fz + uz * Fy;
-        const float t3 = 1.0f / 3.0f;
-        const float f16 = (2.0f * uFx + 2.0f * uFy - uFz) * t3;
-        const float f17 = (2.0f * uFx - uFy + 2.0f * uFz) * t3;
-        const float f18 = (-uFx + 2.0f * uFy + 2.0f * uFz) * t3;
-        // perturbation in moment space: M Omega2 summed over the colours
-        // (Eq. 8), relaxed by S (Eq. 53)
-        const float g2 = st.gx * st.gx + st.gy * st.gy + st.gz * st.gz;
-        float o4 = 0.f, o5 = 0.f, o6 = 0.f, o7 = 0.f, o8 = 0.f, o9 = 0.f, o16 = 0.f, o17 = 0.f, o18 = 0.f;
-        float nx = 0.f, ny = 0.f, nz = 0.f;
-        if (g2 > 1e-24f) {
-            const float ig = rsqrtf(g2);
-            nx = st.gx * ig; ny = st.gy * ig; nz = st.gz * ig;
-            const float ag = C.Asum * ig * (1.0f / 9.0f);
-            const float gxx = st.gx * st.gx, gyy = st.gy * st.gy, gzz = st.gz * st.gz;
-            o4 = -2.0f * ag * g2;
-            o5 = ag * (3.0f * gxx - g2);
-            o6 = ag * (gyy - gzz);
-            o7 = ag * st.gx * st.gy; o8 = ag * st.gx * st.gz; o9 = ag * st.gy * st.gz;
-            o16 = -0.5f * ag * gzz; o17 = -0.5f * ag * gyy; o18 = -0.5f * ag * gxx;
-        }
-        // post-collision moment changes mbar (Eq. 41 + force + Eq. 53); rows
-        // 0-3: mass unchanged, momentum changed by F (exact for the sum)
-        const float he = 1.0f - 0.5f * se, hv = 1.0f - 0.5f * sv, hq = 1.0f - 0.5f * sq, hp = 1.0f - 0.5f * sp;
-        const float b4 = -se * (m4 - e4) + he * (c4 + f4) + se * o4;
-        const float b5 = -sv * (m5 - e5) + hv * (c5 + f5) + sv * o5;
-        const float b6 = -sv * (m6 - e6) + hv * (c6 + f6) + sv * o6;
-        const float b7 = -sv * (m7 - e7) + hv * f7 + sv * o7;
-        const float b8 = -sv * (m8 - e8) + hv * f8 + sv * o8;
-        const float b9 = -sv * (m9 - e9) + hv * f9 + sv * o9;
-        const float b10 = -sq * (m10 - e10) + hq * (Fy * t3);
-        const float b11 = -sq * (m11 - e11) + hq * (Fx * t3);
-        const float b12 = -sq * (m12 - e12) + hq * (Fz * t3);
-        const float b13 = -sq * (m13 - e11) + hq * (Fx * t3);
-        const float b14 = -sq * (m14 - e12) + hq * (Fz * t3);
-        const float b15 = -sq * (m15 - e10) + hq * (Fy * t3);
-        const float b16 = -sp * (m16 - e16) + hp * f16 + sp * o16;
-        const float b17 = -sp * (m17 - e17) + hp * f17 + sp * o17;
-        const float b18 = -sp * (m18 - e18) + hp * f18 + sp * o18;
+__device__ inline int ring_slot(int z) { return (z + 3) % 3; }
 
-        // t = g + M^-1 mbar = f* - sum_k R_k phi^k (sparse closed form of M^-1)
-        float fs[Q];
-        const float q4 = b4 * (1.0f / 6.0f);
-        fs[0] = f[0] - b4 + b16 + b17 + b18;
-        {
-            const float base = q4 + b5 * (1.0f / 6.0f) - 0.5f * (b16 + b17);
-            const float odd = 0.5f * (Fx - b11 - b13);
-            fs[1] = f[1] + base + odd;
-            fs[2] = f[2] + base - odd;
-        }
-        {
-            const float base = q4 - b5 * (1.0f / 12.0f) + 0.25f * b6 - 0.5f * (b16 + b18);
-            const float odd = 0.5f * (Fy - b10 - b15);
-            fs[3] = f[3] + base + odd;
-            fs[4] = f[4] + base - odd;
-        }
-        {
-            const float base = q4 - b5 * (1.0f / 12.0f) - 0.25f * b6 - 0.5f * (b17 + b18);
-            const float odd = 0.5f * (Fz - b12 - b14);
-            fs[5] = f[5] + base + odd;
-            fs[6] = f[6] + base - odd;
-        }
-        fs[7] = f[7] + 0.25f * (b7 + b10 + b11 + b16);
-        fs[8] = f[8] + 0.25f * (b7 - b10 - b11 + b16);
-        fs[9] = f[9] + 0.25f * (-b7 - b10 + b11 + b16);
-        fs[10] = f[10] + 0.25f * (-b7 + b10 - b11 + b16);
-        fs[11] = f[11] + 0.25f * (b8 + b12 + b13 + b17);
-        fs[12] = f[12] + 0.25f * (b8 - b12 - b13 + b17);
-        fs[13] = f[13] + 0.25f * (-b8 - b12 + b13 + b17);
-        fs[14] = f[14] + 0.25f * (-b8 + b12 - b13 + b17);
-        fs[15] = f[15] + 0.25f * (b9 + b14 + b15 + b18);
-        fs[16] = f[16] + 0.25f * (b9 - b14 - b15 + b18);
-        fs[17] = f[17] + 0.25f * (-b9 - b14 + b15 + b18);
-        fs[18] = f[18] + 0.25f * (-b9 + b14 - b15 + b18);
+// aux value of a node from its pulled state
+__device__ inline float4 aux_value(const DevCase &C, const NodeState &s)
+{
+    const Macro m = macro(C, s);
+    const float qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
+    return make_float4(phase_field(C, s.R[0], s.R[1]), m.ux * qs, m.uy * qs, m.uz * qs);
+}
 
-        // recoloring (Eq. 10-11): F0_i = sum_k rho_k phi_i^k is rho_R alpha_R +
-        // rho_B alpha_B at rest, p/6 on the axes and p/12 on the diagonals.
-        // Stored red deviation: rho_R/rho f*_i + seg_i - R_R phi_i^R
-        //   = (rho_R/rho) t_i + seg_i + cr_i,
-        // cr_i = [R_R R_B (phi_i^B - phi_i^R) + eta_R R_B phi_i^B - eta_B R_R phi_i^R]/rho;
-        // blue: t_i - (red deviation).  rho_R/rho is a correctly rounded
-        // quotient (exactly 1 in a pure red node, so pure phases stay pure).
-        const float ir = M.inv_rho;
-        const float RR = s.R[0], RB = s.R[1];
-        const float ar = RR / rho;
-        const float bseg = C.beta * RR * RB * ir * ir;
-        const float sa = bseg * p * (1.0f / 6.0f);
-        const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
-        const float rr = RR * RB;
-        float cr[3];
-        #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            cr[k] = (rr * (C.phi[1][k] - C.phi[0][k]) + s.eta[0] * RB * C.phi[1][k] - s.eta[1] * RR * C.phi[0][k]) * ir;
-        float seg[Q];
-        seg[0] = 0.f;
-        seg[1] = sa * nx; seg[2] = -sa * nx; seg[3] = sa * ny; seg[4] = -sa * ny;
-        seg[5] = sa * nz; seg[6] = -sa * nz;
-        seg[7] = sd * (nx + ny); seg[8] = -seg[7]; seg[9] = sd * (nx - ny); seg[10] = -seg[9];
-        seg[11] = sd * (nx + nz); seg[12] = -seg[11]; seg[13] = sd * (nx - nz); seg[14] = -seg[13];
-        seg[15] = sd * (ny + nz); seg[16] = -seg[15]; seg[17] = sd * (ny - nz); seg[18] = -seg[17];
+template <int I = 1>
+__device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int r, Stencil &st)
+{
+    if constexpr (I < Q) {
+        constexpr int X = ex(I), Y = ey(I), Z = ez(I);
+        constexpr float w3 = ecls(I) == 1 ? (1.0f / 6.0f) : (1.0f / 12.0f);
+        const float4 v = ring[ring_slot(z + Z)][r + X + FRX * Y];
+        if constexpr (X != 0) { st.gx += (X * w3) * v.x; st.Qx += (X * w3) * v.y; }
+        if constexpr (Y != 0) { st.gy += (Y * w3) * v.x; st.Qy += (Y * w3) * v.z; }
+        if constexpr (Z != 0) { st.gz += (Z * w3) * v.x; st.Qz += (Z * w3) * v.w; }
+        stencil_lds<I + 1>(ring, z, r, st);
+    }
+}
 
-        T *outb = reinterpret_cast<T *>(a.fout) + C.pop_off;
-        const size_t N = (size_t)C.N;
-        #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
-            const float db = fs[i] - dr;
-            outb[(size_t)i * N + node] = S::enc(dr, a.scale);
-            outb[(size_t)(Q + i) * N + node] = S::enc(db, a.scale);
+// Fill ring slot of plane zz (-1 <= zz <= nz): pull the tile (keeping the
+// interior state in `keep`) and the halo, or mirror the first layer beyond a
+// wall.
+template <int ST>
+__device__ inline void fused_plane(const StepArgs &a, const DevCase &C, float4 (*ring)[FREG], int zz, int x0,
+                                   int y0, int ax, int ay, bool active, int tx, int ty, NodeState &keep)
+{
+    const int slot = ring_slot(zz);
+    const int tid = (int)threadIdx.x;
+    const int nreg = (ax + 2) * (ay + 2);
+    if (C.wall == 2 && (zz < 0 || zz >= C.nz)) {
+        const int from = ring_slot(zz < 0 ? 0 : C.nz - 1);
+        for (int e = tid; e < nreg; e += blockDim.x) {
+            const int rx = e % (ax + 2), ry = e / (ax + 2);
+            const int r = rx + FRX * ry;
+            const float4 v = ring[from][r];
+            ring[slot][r] = make_float4(v.x, -v.y, -v.z, -v.w);
         }
-        a.rho_cur[C.node_off + node] = make_float2(RR, RB);
+        return;
+    }
+    const int z = zz < 0 ? zz + C.nz : (zz >= C.nz ? zz - C.nz : zz);
+    if (active) {
+        const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
+        const Coord c = make_coord(C, node);
+        pull_node<ST>(a, C, c, keep);
+        ring[slot][(tx + 1) + FRX * (ty + 1)] = aux_value(C, keep);
+    }
+    // halo ring of the active (ax x ay) extent
+    const int nh = 2 * (ax + 2) + 2 * ay;
+    for (int h = tid; h < nh; h += blockDim.x) {
+        int rx, ry;
+        if (h < ax + 2) { rx = h - 1; ry = -1; }
+        else if (h < 2 * (ax + 2)) { rx = h - (ax + 2) - 1; ry = ay; }
+        else if (h < 2 * (ax + 2) + ay) { rx = -1; ry = h - 2 * (ax + 2); }
+        else { rx = ax; ry = h - 2 * (ax + 2) - ay; }
+        int x = x0 + rx, y = y0 + ry;
+        x = x < 0 ? x + C.nx : (x >= C.nx ? x - C.nx : x);
+        y = y < 0 ? y + C.ny : (y >= C.ny ? y - C.ny : y);
+        const Coord c = make_coord(C, x + C.nx * (y + C.ny * z));
+        NodeState hs;
+        pull_node<ST>(a, C, c, hs);
+        ring[slot][(rx + 1) + FRX * (ry + 1)] = aux_value(C, hs);
+    }
+}
+
+template <int ST>
+__global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
+{
+    __shared__ float4 ring[3][FREG];
+    const StepArgs &a = fa.a;
+    const TileRange tr = tile_range(fa.nftiles);
+    const int tx = (int)threadIdx.x % FTX, ty = (int)threadIdx.x / FTX;
+    for (int t = tr.first; t < tr.end; t += tr.stride) {
+        const int4 tl = fa.ftiles[t];
+        const DevCase &C = a.cases[tl.x];
+        const int x0 = tl.y, y0 = tl.z, z0 = tl.w;
+        const int z1 = min(z0 + fa.zc, C.nz);
+        const int ax = min(FTX, C.nx - x0), ay = min(FTY, C.ny - y0);
+        const bool active = tx < ax && ty < ay;
+        const int r = (tx + 1) + FRX * (ty + 1);
+        NodeState cur, nxt;
+        __syncthreads();                       // ring reuse across tiles
+        if (C.wall == 2 && z0 == 0) {
+            fused_plane<ST>(a, C, ring, 0, x0, y0, ax, ay, active, tx, ty, cur);
+            __syncthreads();
+            fused_plane<ST>(a, C, ring, -1, x0, y0, ax, ay, active, tx, ty, nxt);
+        } else {
+            fused_plane<ST>(a, C, ring, z0 - 1, x0, y0, ax, ay, active, tx, ty, nxt);
+            fused_plane<ST>(a, C, ring, z0, x0, y0, ax, ay, active, tx, ty, cur);
+        }
+        for (int z = z0; z < z1; ++z) {
+            fused_plane<ST>(a, C, ring, z + 1, x0, y0, ax, ay, active, tx, ty, nxt);
+            __syncthreads();
+            if (active) {
+                Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                stencil_lds(ring, z, r, st);
+                const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
+                collide_node<ST>(a, C, node, cur, st, ring[ring_slot(z)][r].x);
+            }
+            __syncthreads();
+            cur = nxt;
+        }
     }
 }
 

@@ -59,8 +59,13 @@ struct lbcg_handle {
     std::vector<hipEvent_t> events;
     size_t ev_used = 0;
     std::vector<int3> pending;
-    double ms_acc[3] = {0, 0, 0};
-    int64_t launches[3] = {0, 0, 0};
+    double ms_acc[4] = {0, 0, 0, 0};
+    int64_t launches[4] = {0, 0, 0, 0};
+    // fused single-pass step
+    bool fused = false;
+    int zc = 16;
+    int4 *d_ftiles = nullptr;
+    int nftiles = 0;
 };
 
 namespace {
@@ -187,6 +192,16 @@ template <int ST>
 int launch_step(lbcg_handle *h)
 {
     StepArgs a = args_for(h);
+    if (h->fused) {
+        FusedArgs fa{a, h->d_ftiles, h->nftiles, h->zc};
+        const int grid = h->persistent > 0 ? h->persistent : h->nftiles;
+        int rc = timed(h, 3, [&] { hipLaunchKernelGGL(k_fused<ST>, dim3(grid), dim3(FTX * FTY), 0, h->stream, fa); });
+        if (rc) return rc;
+        HIPCHK(hipGetLastError());
+        h->cur ^= 1;
+        h->steps += 1;
+        return LBCG_OK;
+    }
     const int grid = h->persistent > 0 ? h->persistent : h->ntiles;
     int rc = timed(h, 0, [&] { hipLaunchKernelGGL(k_aux<ST>, dim3(grid), dim3(h->block), 0, h->stream, a); });
     if (!rc && h->has_wall)
@@ -254,6 +269,7 @@ void release(lbcg_handle *h)
     h->events.clear();
     (void)hipFree(h->d_cases);
     (void)hipFree(h->d_tiles);
+    (void)hipFree(h->d_ftiles);
     (void)hipFree(h->d_gtiles);
     (void)hipFree(h->pop[0]);
     (void)hipFree(h->pop[1]);
@@ -329,8 +345,11 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     if (!out) return fail(LBCG_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cases || !init || n_cases < 1) return fail(LBCG_EINVAL, "cases/init NULL or n_cases < 1");
-    lbcg_options o = {LBCG_FP32, 0, 256, 0};
+    lbcg_options o = {LBCG_FP32, 0, 256, 0, LBCG_KERNEL_AUTO, 0};
     if (opt) o = *opt;
+    if (o.kernel < LBCG_KERNEL_AUTO || o.kernel > LBCG_KERNEL_FUSED) return fail(LBCG_EINVAL, "unknown kernel");
+    if (o.zchunk == 0) o.zchunk = 16;
+    if (o.zchunk < 1) return fail(LBCG_EINVAL, "zchunk must be >= 1");
     if (o.storage != LBCG_FP32 && o.storage != LBCG_FP16S && o.storage != LBCG_BF16S)
         return fail(LBCG_EINVAL, "unknown storage format");
     if (o.block_nodes == 0) o.block_nodes = 256;
@@ -374,6 +393,26 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     h->ntiles = (int)tiles.size();
     h->ngtiles = (int)gtiles.size();
 
+    // fused eligibility: walls only on z and neutral there
+    bool eligible = true;
+    for (const DevCase &d : h->dc)
+        if (d.wall == 0 || d.wall == 1 || (d.wall == 2 && (d.cot[0] != 0.0f || d.cot[1] != 0.0f))) eligible = false;
+    if (o.kernel == LBCG_KERNEL_FUSED && !eligible) {
+        delete h;
+        return fail(LBCG_EINVAL, "fused kernel needs walls only on z with theta = 90 deg");
+    }
+    h->fused = eligible && o.kernel != LBCG_KERNEL_TWOPASS;
+    h->zc = o.zchunk;
+    std::vector<int4> ftiles;
+    if (h->fused)
+        for (int c = 0; c < n_cases; ++c) {
+            const DevCase &d = h->dc[c];
+            for (int z0 = 0; z0 < d.nz; z0 += h->zc)
+                for (int y0 = 0; y0 < d.ny; y0 += FTY)
+                    for (int x0 = 0; x0 < d.nx; x0 += FTX) ftiles.push_back(make_int4(c, x0, y0, z0));
+        }
+    h->nftiles = (int)ftiles.size();
+
     auto alloc = [&](void **p, size_t bytes) {
         if (bytes == 0) bytes = 256;
         return hipMalloc(p, bytes) == hipSuccess;
@@ -386,7 +425,8 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
               alloc((void **)&h->aux, sizeof(float4) * h->total_nodes) &&
               alloc((void **)&h->ghost, sizeof(float4) * std::max<int64_t>(1, h->total_ghost)) &&
               alloc((void **)&h->partial, sizeof(double) * 6 * (size_t)h->ntiles) &&
-              alloc((void **)&h->red, sizeof(double) * 8);
+              alloc((void **)&h->red, sizeof(double) * 8) &&
+              alloc((void **)&h->d_ftiles, sizeof(int4) * std::max<size_t>(1, ftiles.size()));
     if (ok)
         ok = alloc((void **)&h->rho2[0], sizeof(float2) * h->total_nodes) &&
              alloc((void **)&h->rho2[1], sizeof(float2) * h->total_nodes);
@@ -401,6 +441,8 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         hipMemcpyAsync(h->d_tiles, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice,
                        h->stream) != hipSuccess ||
         (!gtiles.empty() && hipMemcpyAsync(h->d_gtiles, gtiles.data(), sizeof(int2) * gtiles.size(),
+                                           hipMemcpyHostToDevice, h->stream) != hipSuccess) ||
+        (!ftiles.empty() && hipMemcpyAsync(h->d_ftiles, ftiles.data(), sizeof(int4) * ftiles.size(),
                                            hipMemcpyHostToDevice, h->stream) != hipSuccess))
         rc = fail(LBCG_EDEVICE, "table upload failed");
     for (int c = 0; c < n_cases && rc == LBCG_OK; ++c) rc = init_any(h, c, cases[c], init[c]);
@@ -491,7 +533,7 @@ int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches)
     }
     h->pending.clear();
     h->ev_used = 0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         ms[k] = h->ms_acc[k];
         launches[k] = h->launches[k];
         h->ms_acc[k] = 0.0;

@@ -51,7 +51,12 @@ class lbcg_fields(C.Structure):
 
 class lbcg_options(C.Structure):
     _fields_ = [("storage", C.c_int32), ("diag_every", C.c_int32),
-                ("block_nodes", C.c_int32), ("persistent_blocks", C.c_int32)]
+                ("block_nodes", C.c_int32), ("persistent_blocks", C.c_int32),
+                ("kernel", C.c_int32), ("zchunk", C.c_int32)]
+
+
+LBCG_KERNEL_AUTO, LBCG_KERNEL_TWOPASS, LBCG_KERNEL_FUSED = 0, 1, 2
+KERNEL = {"auto": LBCG_KERNEL_AUTO, "twopass": LBCG_KERNEL_TWOPASS, "fused": LBCG_KERNEL_FUSED}
 
 
 _lib = None
@@ -119,7 +124,8 @@ def _stream_ptr(stream):
     return torch.cuda.current_stream().cuda_stream
 
 
-def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blocks=0, stream=None):
+def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blocks=0, kernel="auto",
+              zchunk=0, stream=None):
     """cases: list of (params, fields) from the workload generators; fields are
     host numpy arrays (FP64).  Returns the opaque handle (an int)."""
     L = load()
@@ -139,7 +145,8 @@ def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blo
         farr[i].rhoR, farr[i].rhoB, farr[i].ux, farr[i].uy, farr[i].uz = ptrs
         farr[i].on_device = 0
     opt = lbcg_options(STORAGE[storage] if isinstance(storage, str) else int(storage),
-                       int(diag_every), int(block_nodes), int(persistent_blocks))
+                       int(diag_every), int(block_nodes), int(persistent_blocks),
+                       KERNEL[kernel] if isinstance(kernel, str) else int(kernel), int(zchunk))
     h = C.c_void_p()
     _check(L.lbcg_init(carr, n, farr, C.byref(opt), C.c_void_p(_stream_ptr(stream)), C.byref(h)))
     return h.value
@@ -184,11 +191,11 @@ def lbcg_timing(h, enable):
 
 
 def lbcg_timing_read(h):
-    """{'aux'|'ghost'|'collide': (total_ms, launches)} since the last read."""
-    ms = (C.c_double * 3)()
-    n = (C.c_int64 * 3)()
+    """{'aux'|'ghost'|'collide'|'fused': (total_ms, launches)} since the last read."""
+    ms = (C.c_double * 4)()
+    n = (C.c_int64 * 4)()
     _check(load().lbcg_timing_read(C.c_void_p(h), ms, n))
-    return {k: (ms[i], int(n[i])) for i, k in enumerate(("aux", "ghost", "collide"))}
+    return {k: (ms[i], int(n[i])) for i, k in enumerate(("aux", "ghost", "collide", "fused"))}
 
 
 def lbcg_index_map(h, case_id):

@@ -183,6 +183,33 @@ def test_batched_uneven_cases_500_steps():
         assert_parity(f"batch500_{c}", batch[c], oracle_run(p, fl, 500), p)
 
 
+@pytest.mark.parametrize("name,maker,zchunk", [
+    ("periodic_ragged", lambda: W.random_state_case(21, 18, 13, seed=41), 5),
+    ("wall_z_neutral", lambda: W.random_state_case(17, 16, 12, seed=42, bc=(0, 0, 1), theta=(90.0, 90.0),
+                                                    grav=(0, 0, -1e-4), rho_ref=2.0), 4),
+    ("column_1x1", lambda: W.layered_channel(1, 1, 24, ratio=10.0, visc_ratio=10.0, G=1e-5), 7),
+    ("thin_x", lambda: W.random_state_case(2, 33, 9, seed=43, force=(1e-5, 0, 0)), 16),
+])
+def test_fused_kernel_matches_two_pass(name, maker, zchunk):
+    """The fused single-pass step and the two-pass step compute the same
+    arithmetic: populations agree bit for bit after 60 steps."""
+    import torch
+    from paper_1904_03618_amd import lbcg as B
+    p, fl = maker()
+    out = {}
+    for kernel in ("twopass", "fused"):
+        h = B.lbcg_init([(p, fl)], kernel=kernel, zchunk=zchunk)
+        try:
+            B.lbcg_step(h, 60)
+            out[kernel] = B.lbcg_get_populations(h, 0).cpu().numpy()
+            torch.cuda.synchronize()
+        finally:
+            B.lbcg_free(h)
+    d = np.abs(out["fused"] - out["twopass"]).max()
+    print(name, "max |fused - twopass| =", d, flush=True)
+    assert np.array_equal(out["fused"], out["twopass"])
+
+
 def test_tile_shape_does_not_change_result():
     """No atomics in the step: tile size and persistent scheduling give
     bitwise identical populations."""
