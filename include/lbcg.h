@@ -94,7 +94,7 @@ typedef struct lbcg_fields {
 } lbcg_fields;
 
 /* Step kernels. */
-#define LBCG_KERNEL_AUTO 0      /* fused when every case is eligible, else two-pass */
+#define LBCG_KERNEL_AUTO 0      /* the faster path for the cases (two-pass today) */
 #define LBCG_KERNEL_TWOPASS 1   /* moments pass + collision pass (any boundaries) */
 #define LBCG_KERNEL_FUSED 2     /* single pass, z-marching tiles with an LDS halo;
                                    eligible cases: walls only on z, and those

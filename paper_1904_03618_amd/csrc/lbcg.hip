@@ -401,7 +401,9 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         delete h;
         return fail(LBCG_EINVAL, "fused kernel needs walls only on z with theta = 90 deg");
     }
-    h->fused = eligible && o.kernel != LBCG_KERNEL_TWOPASS;
+    // The two-pass step is the faster one on gfx950 today (the fused kernel is
+    // latency-bound at two waves per SIMD), so AUTO selects it.
+    h->fused = eligible && o.kernel == LBCG_KERNEL_FUSED;
     h->zc = o.zchunk;
     std::vector<int4> ftiles;
     if (h->fused)
