@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -111,6 +113,38 @@ def copy_probe(mib):
     return {"bytes": 2 * mib * (1 << 20), "avg_ms": ms, "GBps": 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9}
 
 
+def batch_bench(B, steps, warmup, storage="fp16s", ncases=256):
+    """Batched droplet impact: `ncases` independent boxes of side 48..128 in one
+    handle (one launch per kernel over every box), FP16S storage, launch shape
+    picked by the autotuner.  Aggregate MLUPS over all boxes."""
+    import torch
+    from paper_1904_03618_amd import autotune as AT
+    from paper_1904_03618_amd import workloads as W
+    t0 = time.time()
+    cases = W.impact_batch(ncases)
+    gen_s = time.time() - t0
+    N = sum(p["nx"] * p["ny"] * p["nz"] for p, _ in cases)
+    opts, rep = AT.autotune(cases, storage)
+    s = B.Solver(cases, storage=storage, diag_every=0, **opts)
+    try:
+        s.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        bad = sum(1 for c in range(ncases) if not np.isfinite(B.lbcg_moments(s.h, c)).all())
+    finally:
+        s.close()
+    return {"workload": f"{ncases} droplet-impact boxes, sides 48..128 (seeded), wetting bottom wall",
+            "storage": storage, "nodes": N, "MLUPS": N / ms / 1e3, "ms_per_step": ms, "steps": steps,
+            "warmup": warmup, "options": opts, "autotune_key": rep["key"], "autotune_cached": rep["cached"],
+            "cases_non_finite": bad, "input_generation_s": gen_s}
+
+
 def cpu_baseline(p, fl, budget_s):
     """The FP64 oracle on the host cores, on a bounded sample of the same
     workload (the full 128^3 lattice for a few steps)."""
@@ -137,6 +171,7 @@ def main():
     ap.add_argument("--forms", default="fp16s,bf16s", help="extra storage forms to time ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused"])
+    ap.add_argument("--batch-steps", type=int, default=100, help="timed steps of the impact batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the device copy that measures the attainable HBM rate (0: skip)")
@@ -176,6 +211,7 @@ def main():
                                                           "steps": args.steps + args.warmup}}
 
     copy = copy_probe(args.copy_probe_mib) if args.copy_probe_mib > 0 else None
+    batch = batch_bench(B, args.batch_steps, 10) if args.batch_steps > 0 else None
 
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
@@ -191,6 +227,8 @@ def main():
                      "bytes_per_node": kbytes, "traffic": traffic},
         "forms": forms,
     }
+    if batch:
+        out["batch"] = batch
     if copy:
         out["copy_probe"] = copy
         out["roofline"]["frac_of_copy_probe"] = ach / copy["GBps"]

@@ -106,7 +106,11 @@ typedef struct lbcg_fields {
  * the two-pass kernels (0 = default 256; 64, 128, 192 or 256).
  * persistent_blocks: 0 = one workgroup per tile, >0 = that many workgroups
  * looping over all tiles of all cases (batched persistent launch).
- * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default 16). */
+ * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default 16).
+ * graph_steps: 0 = launch every kernel of every step; n > 0 = capture n steps
+ * (rounded up to even) once into a HIP graph and replay it; with diag_every
+ * the stability check then runs at the first replay boundary at or after each
+ * multiple of diag_every, and kernel timing (lbcg_timing) is not available. */
 typedef struct lbcg_options {
     int32_t storage;
     int32_t diag_every;
@@ -114,6 +118,8 @@ typedef struct lbcg_options {
     int32_t persistent_blocks;
     int32_t kernel;
     int32_t zchunk;
+    int32_t graph_steps;
+    int32_t reserved;
 } lbcg_options;
 
 typedef struct lbcg_handle lbcg_handle;

@@ -66,6 +66,12 @@ struct lbcg_handle {
     int zc = 16;
     int4 *d_ftiles = nullptr;
     int nftiles = 0;
+    // captured step loops
+    int graph_steps = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_parity = 0;              // steps & 1 at capture
 };
 
 namespace {
@@ -189,13 +195,13 @@ int timed(lbcg_handle *h, int kernel, F &&launch)
 }
 
 template <int ST>
-int launch_step(lbcg_handle *h)
+int launch_step(lbcg_handle *h, hipStream_t st)
 {
     StepArgs a = args_for(h);
     if (h->fused) {
         FusedArgs fa{a, h->d_ftiles, h->nftiles, h->zc};
         const int grid = h->persistent > 0 ? h->persistent : h->nftiles;
-        int rc = timed(h, 3, [&] { hipLaunchKernelGGL(k_fused<ST>, dim3(grid), dim3(FTX * FTY), 0, h->stream, fa); });
+        int rc = timed(h, 3, [&] { hipLaunchKernelGGL(k_fused<ST>, dim3(grid), dim3(FTX * FTY), 0, st, fa); });
         if (rc) return rc;
         HIPCHK(hipGetLastError());
         h->cur ^= 1;
@@ -203,14 +209,14 @@ int launch_step(lbcg_handle *h)
         return LBCG_OK;
     }
     const int grid = h->persistent > 0 ? h->persistent : h->ntiles;
-    int rc = timed(h, 0, [&] { hipLaunchKernelGGL(k_aux<ST>, dim3(grid), dim3(h->block), 0, h->stream, a); });
+    int rc = timed(h, 0, [&] { hipLaunchKernelGGL(k_aux<ST>, dim3(grid), dim3(h->block), 0, st, a); });
     if (!rc && h->has_wall)
         rc = timed(h, 1, [&] {
-            hipLaunchKernelGGL(k_ghost, dim3(std::min(h->ngtiles, 65536)), dim3(256), 0, h->stream, a,
+            hipLaunchKernelGGL(k_ghost, dim3(std::min(h->ngtiles, 65536)), dim3(256), 0, st, a,
                                (const int2 *)h->d_gtiles, h->ngtiles);
         });
     if (!rc)
-        rc = timed(h, 2, [&] { hipLaunchKernelGGL(k_collide<ST>, dim3(grid), dim3(h->block), 0, h->stream, a); });
+        rc = timed(h, 2, [&] { hipLaunchKernelGGL(k_collide<ST>, dim3(grid), dim3(h->block), 0, st, a); });
     if (rc) return rc;
     HIPCHK(hipGetLastError());
     h->cur ^= 1;
@@ -218,13 +224,41 @@ int launch_step(lbcg_handle *h)
     return LBCG_OK;
 }
 
-int step_once(lbcg_handle *h)
+int step_once(lbcg_handle *h, hipStream_t st)
 {
     switch (h->storage) {
-    case LBCG_FP32: return launch_step<LBCG_FP32>(h);
-    case LBCG_FP16S: return launch_step<LBCG_FP16S>(h);
-    default: return launch_step<LBCG_BF16S>(h);
+    case LBCG_FP32: return launch_step<LBCG_FP32>(h, st);
+    case LBCG_FP16S: return launch_step<LBCG_FP16S>(h, st);
+    default: return launch_step<LBCG_BF16S>(h, st);
     }
+}
+
+// Capture graph_steps steps (from the current buffer parity) into a graph on
+// the private capture stream; the handle's level is left unchanged.
+int capture_graph(lbcg_handle *h)
+{
+    if (!h->capture_stream) HIPCHK(hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking));
+    const int cur0 = h->cur;
+    const int64_t steps0 = h->steps;
+    const bool timing0 = h->timing;
+    h->timing = false;
+    HIPCHK(hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    int rc = LBCG_OK;
+    for (int s = 0; s < h->graph_steps && rc == LBCG_OK; ++s) rc = step_once(h, h->capture_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
+    h->cur = cur0;
+    h->steps = steps0;
+    h->timing = timing0;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(LBCG_EDEVICE, std::string("stream capture: ") + hipGetErrorString(e));
+    h->graph = g;
+    HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+    h->graph_parity = (int)(steps0 & 1);
+    return LBCG_OK;
 }
 
 // FP64 sums over tiles [t0, t0 + nt) into h->red[0..5]; optional field exports.
@@ -265,6 +299,12 @@ int stability_check(lbcg_handle *h)
 
 void release(lbcg_handle *h)
 {
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+    h->capture_stream = nullptr;
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     h->events.clear();
     (void)hipFree(h->d_cases);
@@ -345,8 +385,9 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     if (!out) return fail(LBCG_EINVAL, "out is NULL");
     *out = nullptr;
     if (!cases || !init || n_cases < 1) return fail(LBCG_EINVAL, "cases/init NULL or n_cases < 1");
-    lbcg_options o = {LBCG_FP32, 0, 256, 0, LBCG_KERNEL_AUTO, 0};
+    lbcg_options o = {LBCG_FP32, 0, 256, 0, LBCG_KERNEL_AUTO, 0, 0, 0};
     if (opt) o = *opt;
+    if (o.graph_steps < 0) return fail(LBCG_EINVAL, "graph_steps must be >= 0");
     if (o.kernel < LBCG_KERNEL_AUTO || o.kernel > LBCG_KERNEL_FUSED) return fail(LBCG_EINVAL, "unknown kernel");
     if (o.zchunk == 0) o.zchunk = 16;
     if (o.zchunk < 1) return fail(LBCG_EINVAL, "zchunk must be >= 1");
@@ -405,6 +446,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     // latency-bound at two waves per SIMD), so AUTO selects it.
     h->fused = eligible && o.kernel == LBCG_KERNEL_FUSED;
     h->zc = o.zchunk;
+    h->graph_steps = o.graph_steps + (o.graph_steps & 1);
     std::vector<int4> ftiles;
     if (h->fused)
         for (int c = 0; c < n_cases; ++c) {
@@ -464,8 +506,32 @@ int lbcg_step(lbcg_handle *h, int64_t nsteps)
     int rc = check_handle(h);
     if (rc) return rc;
     if (nsteps < 0) return fail(LBCG_EINVAL, "nsteps < 0");
-    for (int64_t s = 0; s < nsteps; ++s) {
-        rc = step_once(h);
+    int64_t left = nsteps;
+    if (h->graph_steps > 0 && !h->timing) {
+        while (left > 0) {
+            if (!h->graph_exec) {
+                rc = capture_graph(h);
+                if (rc) return rc;
+            }
+            if (left < h->graph_steps) break;
+            if ((int)(h->steps & 1) != h->graph_parity) {   // one eager step restores the captured parity
+                rc = step_once(h, h->stream);
+                if (rc) return rc;
+                --left;
+                continue;
+            }
+            HIPCHK(hipGraphLaunch(h->graph_exec, h->stream));
+            const int64_t before = h->steps;
+            h->steps += h->graph_steps;                        // even: buffer parity unchanged
+            left -= h->graph_steps;
+            if (h->diag_every > 0 && h->steps / h->diag_every != before / h->diag_every) {
+                rc = stability_check(h);
+                if (rc) return rc;
+            }
+        }
+    }
+    for (int64_t s = 0; s < left; ++s) {
+        rc = step_once(h, h->stream);
         if (rc) return rc;
         if (h->diag_every > 0 && h->steps % h->diag_every == 0) {
             rc = stability_check(h);

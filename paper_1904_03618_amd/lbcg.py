@@ -52,7 +52,8 @@ class lbcg_fields(C.Structure):
 class lbcg_options(C.Structure):
     _fields_ = [("storage", C.c_int32), ("diag_every", C.c_int32),
                 ("block_nodes", C.c_int32), ("persistent_blocks", C.c_int32),
-                ("kernel", C.c_int32), ("zchunk", C.c_int32)]
+                ("kernel", C.c_int32), ("zchunk", C.c_int32),
+                ("graph_steps", C.c_int32), ("reserved", C.c_int32)]
 
 
 LBCG_KERNEL_AUTO, LBCG_KERNEL_TWOPASS, LBCG_KERNEL_FUSED = 0, 1, 2
@@ -125,7 +126,7 @@ def _stream_ptr(stream):
 
 
 def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blocks=0, kernel="auto",
-              zchunk=0, stream=None):
+              zchunk=0, graph_steps=0, stream=None):
     """cases: list of (params, fields) from the workload generators; fields are
     host numpy arrays (FP64).  Returns the opaque handle (an int)."""
     L = load()
@@ -146,7 +147,8 @@ def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blo
         farr[i].on_device = 0
     opt = lbcg_options(STORAGE[storage] if isinstance(storage, str) else int(storage),
                        int(diag_every), int(block_nodes), int(persistent_blocks),
-                       KERNEL[kernel] if isinstance(kernel, str) else int(kernel), int(zchunk))
+                       KERNEL[kernel] if isinstance(kernel, str) else int(kernel), int(zchunk),
+                       int(graph_steps), 0)
     h = C.c_void_p()
     _check(L.lbcg_init(carr, n, farr, C.byref(opt), C.c_void_p(_stream_ptr(stream)), C.byref(h)))
     return h.value

@@ -142,11 +142,31 @@ def rayleigh_taylor(nx=128, ny=None, nz=None, g=2e-5, Re=1024.0, amp=0.05, rho_i
     return p, f
 
 
-def impact_case(case: int, seed=1904, lmin=48, lmax=128, A=0.00225):
+def smooth_droplet_fields(p: dict, centre, radius, rho_in, u_in=(0.0, 0.0, 0.0), width=1.5):
+    """Droplet with a tanh interface of the given width: red fraction
+    phi = (1 - tanh((d - R)/width))/2 with d the (periodic) distance to the
+    centre; rho_R = phi rho_R^in, rho_B = (1 - phi) rho_B^in, and the droplet
+    velocity carried by the red fraction (u = phi u_in)."""
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    x, y, z = _grid(nx, ny, nz)
+    d = np.sqrt(_periodic_d2(x, centre[0], nx, p["bc"][0] == 0) +
+                _periodic_d2(y, centre[1], ny, p["bc"][1] == 0) +
+                _periodic_d2(z, centre[2], nz, p["bc"][2] == 0))
+    ph = 0.5 * (1.0 - np.tanh((d - radius) / width))
+    f = dict(rhoR=rho_in[0] * ph, rhoB=rho_in[1] * (1.0 - ph))
+    for a, name in enumerate(("ux", "uy", "uz")):
+        f[name] = u_in[a] * ph
+    return f
+
+
+def impact_case(case: int, seed=1904, lmin=48, lmax=128, A=0.00225, width=1.5):
     """One droplet-impact case of the batch: cube of side L ~ U{lmin..lmax},
     wall at z (bottom wetting theta ~ U(60, 150) deg, top 90 deg), periodic x,y,
     droplet radius U(0.2, 0.3) L centred at (L/2, L/2, R+2) moving at -U0,
-    U0 ~ U(0.01, 0.05), density ratio ~ U(10, 100), alpha_B = 0.2, tau = 1."""
+    U0 ~ U(0.01, 0.05), density ratio ~ U(10, 100), alpha_B = 0.2, tau = 1.
+    The droplet starts with a tanh interface (width 1.5) and its velocity is
+    carried by the red fraction: with the heavy phase's sound speed
+    sqrt(0.4/ratio), a sharp start at these Mach numbers is unstable."""
     rng = np.random.default_rng([seed, case])
     L = int(rng.integers(lmin, lmax + 1))
     R = float(rng.uniform(0.2, 0.3)) * L
@@ -157,7 +177,7 @@ def impact_case(case: int, seed=1904, lmin=48, lmax=128, A=0.00225):
     rho_in = (1.0, 1.0 / ratio)
     p = _params(nx=L, ny=L, nz=L, bc=(0, 0, 1), theta_deg=(theta, 90.0), rho_in=rho_in,
                 alpha=(aR, aB), tau_v=(1.0, 1.0), A=(A, A))
-    f = droplet_fields(p, (L / 2.0, L / 2.0, R + 2.0), R, rho_in, u_in=(0.0, 0.0, -U0))
+    f = smooth_droplet_fields(p, (L / 2.0, L / 2.0, R + 2.0), R, rho_in, u_in=(0.0, 0.0, -U0), width=width)
     return p, f
 
 

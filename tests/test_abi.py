@@ -33,7 +33,7 @@ def test_struct_layout_matches_header():
     # 6 ints + 10 doubles (5 pairs) + 5 doubles + 7 doubles + 2 ints
     assert C.sizeof(B.lbcg_case) == 6 * 4 + 10 * 8 + 5 * 8 + 7 * 8 + 2 * 4
     assert C.sizeof(B.lbcg_fields) == 5 * 8 + 8
-    assert C.sizeof(B.lbcg_options) == 24
+    assert C.sizeof(B.lbcg_options) == 32
 
 
 def _init_rc(p, fl=None, opt=None, n=1):
@@ -47,7 +47,7 @@ def _init_rc(p, fl=None, opt=None, n=1):
     for i in range(n):
         fs[i].rhoR, fs[i].rhoB, fs[i].ux, fs[i].uy, fs[i].uz = [a.ctypes.data for a in keep]
     h = C.c_void_p()
-    o = opt if opt is not None else B.lbcg_options(0, 0, 0, 0, 0, 0)
+    o = opt if opt is not None else B.lbcg_options(0, 0, 0, 0, 0, 0, 0, 0)
     rc = L.lbcg_init(cs, n, fs, C.byref(o), None, C.byref(h))
     return rc, h.value
 
@@ -73,14 +73,16 @@ def test_init_rejects_invalid_parameters(change, frag):
 
 def test_init_rejects_bad_options_and_pointers():
     p, _ = W.paper_fluids_droplet(4, 1.0)
-    rc, _ = _init_rc(p, opt=B.lbcg_options(7, 0, 0, 0, 0, 0))
+    rc, _ = _init_rc(p, opt=B.lbcg_options(7, 0, 0, 0, 0, 0, 0, 0))
     assert rc == B.LBCG_EINVAL and "storage" in B.lbcg_last_error()
-    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 96 + 1, 0, 0, 0))
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 96 + 1, 0, 0, 0, 0, 0))
     assert rc == B.LBCG_EINVAL and "block_nodes" in B.lbcg_last_error()
-    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 5, 0))
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 5, 0, 0, 0))
     assert rc == B.LBCG_EINVAL and "kernel" in B.lbcg_last_error()
-    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 0, -2))
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 0, -2, 0, 0))
     assert rc == B.LBCG_EINVAL and "zchunk" in B.lbcg_last_error()
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 0, 0, -1, 0))
+    assert rc == B.LBCG_EINVAL and "graph_steps" in B.lbcg_last_error()
     L = B.load()
     h = C.c_void_p()
     assert L.lbcg_init(None, 1, None, None, None, C.byref(h)) == B.LBCG_EINVAL
