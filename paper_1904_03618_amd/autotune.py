@@ -13,7 +13,7 @@ import json
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_CACHE = os.path.join(PKG, "autotune_cache.json")
+DEFAULT_CACHE = os.environ.get("LBCG_AUTOTUNE_CACHE", os.path.join(PKG, "autotune_cache.json"))
 
 
 def box_class(cases, storage):
