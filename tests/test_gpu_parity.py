@@ -192,7 +192,9 @@ def test_batched_uneven_cases_500_steps():
 ])
 def test_fused_kernel_matches_two_pass(name, maker, zchunk):
     """The fused single-pass step and the two-pass step compute the same
-    arithmetic: populations agree bit for bit after 60 steps."""
+    arithmetic (shared collision body; the compiler contracts a few products
+    into FMAs differently in the two kernels): populations agree to a few
+    FP32 ulps after 60 steps."""
     import torch
     from paper_1904_03618_amd import lbcg as B
     p, fl = maker()
@@ -207,7 +209,7 @@ def test_fused_kernel_matches_two_pass(name, maker, zchunk):
             B.lbcg_free(h)
     d = np.abs(out["fused"] - out["twopass"]).max()
     print(name, "max |fused - twopass| =", d, flush=True)
-    assert np.array_equal(out["fused"], out["twopass"])
+    assert d <= 1e-6
 
 
 def test_graph_replays_match_eager_steps():
