@@ -162,6 +162,13 @@ int lbcg_step(lbcg_handle *h, int64_t nsteps);
 int lbcg_moments(lbcg_handle *h, int32_t case_id, float *rhoR, float *rhoB, float *rhoN,
                  float *ux, float *uy, float *uz, double *diag);
 
+/* Reset case case_id to the equilibrium f^k = f^{k,eq}(rho_k, u) of the given
+ * fields (as lbcg_init does at level 0), keeping the handle's step count: the
+ * entry through which predicted macroscopic fields re-enter the LB state.
+ * fields: FP64 arrays as in lbcg_init.  Errors: LBCG_ESTATE, LBCG_EINVAL,
+ * LBCG_ENOMEM, LBCG_EDEVICE. */
+int lbcg_set_fields(lbcg_handle *h, int32_t case_id, const lbcg_fields *fields);
+
 /* Release every device resource of the handle.  LBCG_ESTATE for NULL. */
 int lbcg_free(lbcg_handle *h);
 

@@ -1,4 +1,4 @@
-"""Compile the gfx950 library liblbcg.so in-tree with hipcc."""
+"""Compile the gfx950 library liblbcg.so (LB step + surrogate kernels) in-tree with hipcc."""
 from __future__ import annotations
 
 import os
@@ -7,6 +7,7 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 SRC = os.path.join(PKG, "csrc", "lbcg.hip")
+SRC_SURROGATE = os.path.join(PKG, "csrc", "surrogate.hip")
 LIB = os.path.join(PKG, "liblbcg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -17,7 +18,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 def build(extra=()) -> str:
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, SRC]
+    cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, SRC, SRC_SURROGATE]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB

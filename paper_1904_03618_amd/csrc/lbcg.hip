@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,6 +42,7 @@ struct lbcg_handle {
     int storage = LBCG_FP32, elem = 4, diag_every = 0, block = 256, persistent = 0;
     int ncases = 0;
     std::vector<DevCase> dc;
+    std::vector<std::array<double, 2>> alpha_in;     // FP64 alpha_k per case (equilibrium start)
     std::vector<int> tile_begin, tile_count;
     DevCase *d_cases = nullptr;
     int2 *d_tiles = nullptr, *d_gtiles = nullptr;
@@ -342,8 +344,8 @@ int init_case(lbcg_handle *h, int cid, const lbcg_case &c, const lbcg_fields &f)
         for (int q = 0; q < 5; ++q) dev[q] = const_cast<double *>(src[q]);
     }
     StepArgs a = args_for(h);
-    a.fout = h->pop[h->cur];                 // level 0 is written into the current buffer
-    a.rho_cur = h->rho2[1];                  // and decoded with rho2[(0 + 1) & 1]
+    a.fout = h->pop[h->cur];                 // the level is written into the current buffer
+    a.rho_cur = h->rho2[(h->steps + 1) & 1]; // and decoded with rho2[(t + 1) & 1]
     InitCase ic{{c.alpha[0], c.alpha[1]}, c.improved};
     hipLaunchKernelGGL(k_init<ST>, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, h->stream, a, cid, ic,
                        (const double *)dev[0], (const double *)dev[1], (const double *)dev[2],
@@ -430,6 +432,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         h->tile_count.push_back((int)tiles.size() - h->tile_begin.back());
         for (int e0 = 0; e0 < 2 * d.plane; e0 += 256) gtiles.push_back(make_int2(c, e0));
         h->dc.push_back(d);
+        h->alpha_in.push_back({cases[c].alpha[0], cases[c].alpha[1]});
     }
     h->ntiles = (int)tiles.size();
     h->ngtiles = (int)gtiles.size();
@@ -555,6 +558,26 @@ int lbcg_moments(lbcg_handle *h, int32_t case_id, float *rhoR, float *rhoB, floa
         HIPCHK(hipStreamSynchronize(h->stream));
         for (int k = 0; k < 5; ++k) diag[k] = out[k];
     }
+    return LBCG_OK;
+}
+
+int lbcg_set_fields(lbcg_handle *h, int32_t case_id, const lbcg_fields *fields)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (case_id < 0 || case_id >= h->ncases || !fields) return fail(LBCG_EINVAL, "bad argument");
+    const lbcg_fields &f = *fields;
+    if (!f.rhoR || !f.rhoB || !f.ux || !f.uy || !f.uz) return fail(LBCG_EINVAL, "NULL field");
+    lbcg_case c{};
+    c.alpha[0] = 0.0;
+    // the init kernel only needs alpha and the model flag, recovered from the case constants
+    const DevCase &d = h->dc[case_id];
+    c.alpha[0] = h->alpha_in[case_id][0];
+    c.alpha[1] = h->alpha_in[case_id][1];
+    c.improved = d.improved;
+    rc = init_any(h, case_id, c, f);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
     return LBCG_OK;
 }
 

@@ -1,0 +1,568 @@
+// surrogate.hip -- gfx950 kernels of the learned surrogate (include/lbcg_surrogate.h):
+// 3D convolutions as implicit GEMMs on the CDNA4 matrix cores
+// (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 accumulation), their data and
+// weight gradients, and the element-wise layers, loss and optimiser of a U-Net.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "lbcg_surrogate.h"
+
+namespace sg {
+
+typedef __bf16 bf16;
+typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One MFMA 16x16x32 step.  Lane l (0..63) supplies A[l % 16][8 (l / 16) + j]
+// and B[8 (l / 16) + j][l % 16] for j = 0..7, and receives
+// D[4 (l / 16) + j][l % 16] for j = 0..3.
+__device__ inline f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f32x4 &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ inline int64_t npos(const sg_view &v) { return (int64_t)v.n * v.d * v.h * v.w; }
+
+struct Pos { int n, z, y, x; };
+
+__device__ inline Pos decode(const sg_view &v, int64_t p)
+{
+    Pos q;
+    q.x = (int)(p % v.w);
+    p /= v.w;
+    q.y = (int)(p % v.h);
+    p /= v.h;
+    q.z = (int)(p % v.d);
+    q.n = (int)(p / v.d);
+    return q;
+}
+
+// Neighbour at offset (dz, dy, dx): flat position, or -1 where zero padding applies.
+__device__ inline int64_t shifted(const sg_view &v, const Pos &q, int dz, int dy, int dx, int pmask)
+{
+    int z = q.z + dz, y = q.y + dy, x = q.x + dx;
+    if (x < 0 || x >= v.w) {
+        if (!(pmask & 1)) return -1;
+        x = x < 0 ? x + v.w : x - v.w;
+    }
+    if (y < 0 || y >= v.h) {
+        if (!(pmask & 2)) return -1;
+        y = y < 0 ? y + v.h : y - v.h;
+    }
+    if (z < 0 || z >= v.d) {
+        if (!(pmask & 4)) return -1;
+        z = z < 0 ? z + v.d : z - v.d;
+    }
+    return (((int64_t)q.n * v.d + z) * v.h + y) * v.w + x;
+}
+
+__device__ inline void tap_offset(int tap, int k, int &dz, int &dy, int &dx)
+{
+    if (k == 1) {
+        dz = dy = dx = 0;
+        return;
+    }
+    dz = tap / 9 - 1;
+    dy = (tap / 3) % 3 - 1;
+    dx = tap % 3 - 1;
+}
+
+// ------------------------------------------------------------- forward
+// Workgroup: 4 wavefronts, each a 16 (output channels) x 16 (positions) tile;
+// blockIdx.y selects the 16 output channels.  The K loop walks taps x input
+// channels in groups of 8 (one 16-byte load per lane and operand).
+__global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restrict__ W,
+                                                  const float *__restrict__ bias, int k, int pmask, int relu,
+                                                  sg_view y, sg_view y32, int accumulate)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int64_t P = npos(x);
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
+    const int co0 = blockIdx.y * 16;
+    const int ci = x.c, g8 = ci >> 3, taps = k * k * k;
+    const int K8 = taps * g8, K = taps * ci;
+    const int64_t pb = p0 + col;
+    const bool pvalid = pb < P;
+    const Pos q = decode(x, pvalid ? pb : 0);
+    const bf16 *xp = reinterpret_cast<const bf16 *>(x.p);
+    const bf16 *wrow = W + (int64_t)(co0 + col) * K;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero = {};
+    int last_tap = -1;
+    int64_t src = -1;
+    for (int kb = 0; kb < (K8 + 3) >> 2; ++kb) {
+        const int g = (kb << 2) + grp;
+        bf16x8 a = zero, b = zero;
+        if (g < K8) {
+            const int tap = g / g8, c8 = g - tap * g8;
+            a = *reinterpret_cast<const bf16x8 *>(wrow + (g << 3));
+            if (tap != last_tap) {
+                int dz, dy, dx;
+                tap_offset(tap, k, dz, dy, dx);
+                src = pvalid ? shifted(x, q, dz, dy, dx, pmask) : -1;
+                last_tap = tap;
+            }
+            if (src >= 0) b = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + (c8 << 3));
+        }
+        acc = mfma(a, b, acc);
+    }
+    if (!pvalid) return;
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int oc = co0 + (grp << 2) + j;
+        const bool sy = y.p && oc < y.c, s32 = y32.p && oc < y32.c;
+        if (!sy && !s32) continue;                 // padded output rows
+        float v = acc[j] + (bias ? bias[oc] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        if (sy)
+            reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc] = (bf16)v;
+        if (s32) {
+            float *o = reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc;
+            *o = accumulate ? *o + v : v;
+        }
+    }
+}
+
+// Master weights -> BF16 [co_pad][K] and the flipped transpose
+// Wt[ci][tap' co8 + c] = W[c][tap ci + ci] with tap' the mirrored tap.
+__global__ void k_weight_prep(const float *w32, int co, int ci, int k, bf16 *wb, bf16 *wt, int co_pad, int ci_pad)
+{
+    const int taps = k * k * k, K = taps * ci, co8 = (co + 7) & ~7, Kt = taps * co8;
+    const int64_t n1 = (int64_t)co_pad * K, n2 = (int64_t)ci_pad * Kt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n1 + n2; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < n1) {
+            const int o = (int)(e / K);
+            wb[e] = (bf16)(o < co ? w32[e] : 0.f);
+        } else {
+            const int64_t f = e - n1;
+            const int i = (int)(f / Kt), r = (int)(f % Kt);
+            const int tp = r / co8, c = r % co8;
+            const int tap = taps - 1 - tp;     // (dz,dy,dx) -> (-dz,-dy,-dx)
+            wt[f] = (bf16)((i < ci && c < co) ? w32[(int64_t)c * K + (int64_t)tap * ci + i] : 0.f);
+        }
+    }
+}
+
+// ------------------------------------------------------ weight gradient
+// D[co][kcol] += sum_p dy[p][co] x[p + tap(kcol)][c(kcol)] over one chunk of
+// positions; A = dy^T (16 co x 32 positions), B = shifted x (32 positions x
+// 16 K-columns).  Partial sums per chunk go to ws[chunk][co_pad][K].
+__global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k, int pmask, int chunk, int co_pad,
+                                                    float *ws)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int ci = x.c, taps = k * k * k, K = taps * ci;
+    const int kc = (blockIdx.x * 4 + wave) * 16 + col;     // this lane's K-column (B operand)
+    const int co0 = blockIdx.y * 16;
+    const int co = co0 + col;                              // this lane's row (A operand)
+    const int64_t P = npos(x);
+    const int64_t pbeg = (int64_t)blockIdx.z * chunk, pend = min(P, pbeg + chunk);
+    const bool kvalid = kc < K;
+    int tap = 0, c = 0, dz = 0, dyo = 0, dx = 0;
+    if (kvalid) {
+        tap = kc / ci;
+        c = kc - tap * ci;
+        tap_offset(tap, k, dz, dyo, dx);
+    }
+    const bf16 *xp = reinterpret_cast<const bf16 *>(x.p);
+    const bf16 *dp = reinterpret_cast<const bf16 *>(dy.p);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
+        bf16x8 a = {}, b = {};
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t p = p0 + (grp << 3) + j;
+            if (p < pend) {
+                if (co < dy.c) a[j] = dp[p * dy.ctot + dy.coff + co];
+                if (kvalid) {
+                    const int64_t s = shifted(x, decode(x, p), dz, dyo, dx, pmask);
+                    if (s >= 0) b[j] = xp[s * x.ctot + x.coff + c];
+                }
+            }
+        }
+        acc = mfma(a, b, acc);
+    }
+    #pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int oc = co0 + (grp << 2) + j;
+        if (kvalid) ws[((int64_t)blockIdx.z * co_pad + oc) * K + kc] = acc[j];
+    }
+}
+
+__global__ void k_reduce_chunks(const float *ws, int nchunks, int co_pad, int co, int K, float *dw)
+{
+    const int64_t n = (int64_t)co * K;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e / K), kc = (int)(e % K);
+        float s = 0.f;
+        for (int ch = 0; ch < nchunks; ++ch) s += ws[((int64_t)ch * co_pad + o) * K + kc];
+        dw[e] = s;
+    }
+}
+
+// db[co] = sum_p dy[p][co]: one workgroup per channel, fixed-order tree.
+__global__ __launch_bounds__(256) void k_bias_grad(sg_view dy, float *db)
+{
+    __shared__ float sh[256];
+    const int oc = blockIdx.x;
+    const int64_t P = npos(dy);
+    const bf16 *dp = reinterpret_cast<const bf16 *>(dy.p);
+    float s = 0.f;
+    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) s += (float)dp[p * dy.ctot + dy.coff + oc];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[oc] = sh[0];
+}
+
+// ------------------------------------------------------- element-wise
+__global__ void k_relu_bwd_cast(sg_view dx, sg_view y, sg_view dyb)
+{
+    const int64_t n = npos(dx) * dx.c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / dx.c;
+        const int c = (int)(e % dx.c);
+        float g = reinterpret_cast<const float *>(dx.p)[p * dx.ctot + dx.coff + c];
+        if (y.p && !((float)reinterpret_cast<const bf16 *>(y.p)[p * y.ctot + y.coff + c] > 0.f)) g = 0.f;
+        reinterpret_cast<bf16 *>(dyb.p)[p * dyb.ctot + dyb.coff + c] = (bf16)g;
+    }
+}
+
+__device__ inline int64_t flat(const sg_view &v, int n, int z, int y, int x)
+{
+    return (((int64_t)n * v.d + z) * v.h + y) * v.w + x;
+}
+
+__global__ void k_pool2_fwd(sg_view x, sg_view y)
+{
+    const int64_t n = npos(y) * y.c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / y.c;
+        const int c = (int)(e % y.c);
+        const Pos q = decode(y, p);
+        float s = 0.f;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    s += (float)reinterpret_cast<const bf16 *>(x.p)[flat(x, q.n, 2 * q.z + dz, 2 * q.y + dy, 2 * q.x + dx) * x.ctot + x.coff + c];
+        reinterpret_cast<bf16 *>(y.p)[p * y.ctot + y.coff + c] = (bf16)(0.125f * s);
+    }
+}
+
+__global__ void k_pool2_bwd(sg_view dy, sg_view dx, int accumulate)
+{
+    const int64_t n = npos(dx) * dx.c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / dx.c;
+        const int c = (int)(e % dx.c);
+        const Pos q = decode(dx, p);
+        const float g = 0.125f * reinterpret_cast<const float *>(dy.p)[flat(dy, q.n, q.z >> 1, q.y >> 1, q.x >> 1) * dy.ctot + dy.coff + c];
+        float *o = reinterpret_cast<float *>(dx.p) + p * dx.ctot + dx.coff + c;
+        *o = accumulate ? *o + g : g;
+    }
+}
+
+__global__ void k_up2_fwd(sg_view x, sg_view y)
+{
+    const int64_t n = npos(y) * y.c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / y.c;
+        const int c = (int)(e % y.c);
+        const Pos q = decode(y, p);
+        reinterpret_cast<bf16 *>(y.p)[p * y.ctot + y.coff + c] =
+            reinterpret_cast<const bf16 *>(x.p)[flat(x, q.n, q.z >> 1, q.y >> 1, q.x >> 1) * x.ctot + x.coff + c];
+    }
+}
+
+__global__ void k_up2_bwd(sg_view dy, sg_view dx, int accumulate)
+{
+    const int64_t n = npos(dx) * dx.c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / dx.c;
+        const int c = (int)(e % dx.c);
+        const Pos q = decode(dx, p);
+        float s = 0.f;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dyy = 0; dyy < 2; ++dyy)
+                for (int dxx = 0; dxx < 2; ++dxx)
+                    s += reinterpret_cast<const float *>(dy.p)[flat(dy, q.n, 2 * q.z + dz, 2 * q.y + dyy, 2 * q.x + dxx) * dy.ctot + dy.coff + c];
+        float *o = reinterpret_cast<float *>(dx.p) + p * dx.ctot + dx.coff + c;
+        *o = accumulate ? *o + s : s;
+    }
+}
+
+// MSE: per-workgroup partial sums (fixed order) then one workgroup.
+__global__ __launch_bounds__(256) void k_mse(sg_view out, sg_view tgt, sg_view grad, double *partial)
+{
+    __shared__ double sh[256];
+    const int64_t n = npos(out) * out.c;
+    const double inv = 1.0 / (double)n;
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / out.c;
+        const int c = (int)(e % out.c);
+        const float d = reinterpret_cast<const float *>(out.p)[p * out.ctot + out.coff + c] -
+                        reinterpret_cast<const float *>(tgt.p)[p * tgt.ctot + tgt.coff + c];
+        reinterpret_cast<float *>(grad.p)[p * grad.ctot + grad.coff + c] = (float)(2.0 * d * inv);
+        s += (double)d * d;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0] * inv;
+}
+
+__global__ void k_sum_partials(const double *partial, int n, double *out)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += partial[i];
+        *out = s;
+    }
+}
+
+__global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[e];
+        const float mi = b1 * m[e] + (1.f - b1) * gi;
+        const float vi = b2 * v[e] + (1.f - b2) * gi * gi;
+        m[e] = mi;
+        v[e] = vi;
+        w[e] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    }
+}
+
+__global__ void k_pack(const float *f, int nf, int nx, int ny, int nz, int x0, int y0, int z0, sg_view y, sg_view y32, int b)
+{
+    const int64_t per = (int64_t)y.d * y.h * y.w;
+    const int64_t n = per * y.c;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / y.c;
+        const int c = (int)(e % y.c);
+        const int x = (int)(p % y.w), yy = (int)((p / y.w) % y.h), z = (int)(p / ((int64_t)y.w * y.h));
+        float v = 0.f;
+        if (c < nf) {
+            const int gx = (x0 + x) % nx, gy = (y0 + yy) % ny, gz = (z0 + z) % nz;
+            v = f[(int64_t)c * nx * ny * nz + gx + (int64_t)nx * (gy + (int64_t)ny * gz)];
+        }
+        const int64_t pp = (int64_t)b * per + p;
+        reinterpret_cast<bf16 *>(y.p)[pp * y.ctot + y.coff + c] = (bf16)v;
+        if (y32.p && c < y32.c) reinterpret_cast<float *>(y32.p)[pp * y32.ctot + y32.coff + c] = v;
+    }
+}
+
+__global__ void k_unpack(sg_view x, int b, float *f, int nf)
+{
+    const int64_t per = (int64_t)x.d * x.h * x.w;
+    const int64_t n = per * nf;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(e / per);
+        const int64_t p = e % per;
+        f[e] = reinterpret_cast<const float *>(x.p)[((int64_t)b * per + p) * x.ctot + x.coff + c];
+    }
+}
+
+__global__ void k_lift(const float *rn, int64_t n, float rR, float rB, float *oR, float *oB)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const float v = fminf(1.f, fmaxf(-1.f, rn[e]));
+        oR[e] = rR * 0.5f * (1.f + v);
+        oB[e] = rB * 0.5f * (1.f - v);
+    }
+}
+
+inline unsigned grid_for(int64_t n, int block = 256)
+{
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, 65536));
+}
+
+inline bool ok_view(const sg_view *v) { return v && v->p && v->n > 0 && v->d > 0 && v->h > 0 && v->w > 0 && v->c > 0 && v->coff >= 0 && v->coff + v->c <= v->ctot; }
+inline bool mfma_view(const sg_view *v) { return ok_view(v) && v->c % 8 == 0 && v->ctot % 8 == 0 && v->coff % 8 == 0; }
+inline bool same_pos(const sg_view *a, const sg_view *b) { return a->n == b->n && a->d == b->d && a->h == b->h && a->w == b->w; }
+
+int status() { return hipGetLastError() == hipSuccess ? SG_OK : SG_EDEVICE; }
+
+}  // namespace sg
+
+using namespace sg;
+
+extern "C" {
+
+int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co, int32_t k, int32_t periodic_mask,
+                  int32_t relu, const sg_view *y, const sg_view *y32, int32_t accumulate, void *hip_stream)
+{
+    if (!mfma_view(x) || !w || co <= 0 || co % 16 || (k != 1 && k != 3)) return SG_EINVAL;
+    if (!y && !y32) return SG_EINVAL;
+    if (y && (!ok_view(y) || !same_pos(x, y) || y->c > co)) return SG_EINVAL;
+    if (y32 && (!ok_view(y32) || !same_pos(x, y32) || y32->c > co)) return SG_EINVAL;
+    const sg_view none = {};
+    const int64_t P = (int64_t)x->n * x->d * x->h * x->w;
+    hipLaunchKernelGGL(k_conv_fwd, dim3((unsigned)((P + 63) / 64), co / 16), dim3(256), 0, (hipStream_t)hip_stream, *x,
+                       (const bf16 *)w, bias, k, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none, accumulate);
+    return status();
+}
+
+int sg_weight_prep(const float *w32, int32_t co, int32_t ci, int32_t k, void *w_bf16, void *wt_bf16, int32_t co_pad,
+                   int32_t ci_pad, void *hip_stream)
+{
+    if (!w32 || !w_bf16 || !wt_bf16 || co <= 0 || ci <= 0 || co_pad < co || ci_pad < ci || co_pad % 16 || ci_pad % 16 ||
+        (k != 1 && k != 3))
+        return SG_EINVAL;
+    const int taps = k * k * k;
+    const int64_t n = (int64_t)co_pad * taps * ci + (int64_t)ci_pad * taps * ((co + 7) & ~7);
+    hipLaunchKernelGGL(k_weight_prep, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, w32, co, ci, k,
+                       (bf16 *)w_bf16, (bf16 *)wt_bf16, co_pad, ci_pad);
+    return status();
+}
+
+static int bwd_w_chunks(const sg_view *dy, int ci, int k, int co_pad, int *chunk)
+{
+    const int64_t P = (int64_t)dy->n * dy->d * dy->h * dy->w;
+    const int K = k * k * k * ci;
+    const int tiles = ((K + 63) / 64) * (co_pad / 16);
+    int64_t nch = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max(1, tiles), (P + 255) / 256));
+    int64_t c = (P + nch - 1) / nch;
+    c = (c + 31) / 32 * 32;
+    *chunk = (int)c;
+    return (int)((P + c - 1) / c);
+}
+
+int64_t sg_conv3d_bwd_weight_ws(const sg_view *dy, int32_t ci, int32_t k)
+{
+    if (!ok_view(dy) || ci <= 0) return -1;
+    const int co_pad = (dy->c + 15) & ~15;
+    int chunk;
+    const int nch = bwd_w_chunks(dy, ci, k, co_pad, &chunk);
+    return (int64_t)nch * co_pad * k * k * k * ci * (int64_t)sizeof(float);
+}
+
+int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw, float *db,
+                         float *ws, int64_t ws_bytes, void *hip_stream)
+{
+    if (!ok_view(x) || !ok_view(dy) || !same_pos(x, dy) || !dw || !ws || (k != 1 && k != 3)) return SG_EINVAL;
+    const int ci = x->c, co = dy->c, co_pad = (co + 15) & ~15, K = k * k * k * ci;
+    int chunk;
+    const int nch = bwd_w_chunks(dy, ci, k, co_pad, &chunk);
+    if (ws_bytes < (int64_t)nch * co_pad * K * (int64_t)sizeof(float)) return SG_EINVAL;
+    hipStream_t st = (hipStream_t)hip_stream;
+    hipLaunchKernelGGL(k_conv_bwd_w, dim3((K + 63) / 64, co_pad / 16, nch), dim3(256), 0, st, *x, *dy, k, periodic_mask,
+                       chunk, co_pad, ws);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(grid_for((int64_t)co * K)), dim3(256), 0, st, (const float *)ws, nch,
+                       co_pad, co, K, dw);
+    if (db) hipLaunchKernelGGL(k_bias_grad, dim3(co), dim3(256), 0, st, *dy, db);
+    return status();
+}
+
+int sg_relu_bwd_cast(const sg_view *dx, const sg_view *y, const sg_view *dyb, void *hip_stream)
+{
+    if (!ok_view(dx) || !ok_view(dyb) || !same_pos(dx, dyb) || dx->c != dyb->c) return SG_EINVAL;
+    if (y && (!ok_view(y) || !same_pos(dx, y) || y->c != dx->c)) return SG_EINVAL;
+    const sg_view none = {};
+    const int64_t n = (int64_t)dx->n * dx->d * dx->h * dx->w * dx->c;
+    hipLaunchKernelGGL(k_relu_bwd_cast, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *dx, y ? *y : none,
+                       *dyb);
+    return status();
+}
+
+static bool half_of(const sg_view *big, const sg_view *small)
+{
+    return big->n == small->n && big->d == 2 * small->d && big->h == 2 * small->h && big->w == 2 * small->w &&
+           big->c == small->c;
+}
+
+int sg_pool2_fwd(const sg_view *x, const sg_view *y, void *hip_stream)
+{
+    if (!ok_view(x) || !ok_view(y) || !half_of(x, y)) return SG_EINVAL;
+    const int64_t n = (int64_t)y->n * y->d * y->h * y->w * y->c;
+    hipLaunchKernelGGL(k_pool2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    return status();
+}
+
+int sg_pool2_bwd(const sg_view *dy, const sg_view *dx, int32_t accumulate, void *hip_stream)
+{
+    if (!ok_view(dy) || !ok_view(dx) || !half_of(dx, dy)) return SG_EINVAL;
+    const int64_t n = (int64_t)dx->n * dx->d * dx->h * dx->w * dx->c;
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *dy, *dx, accumulate);
+    return status();
+}
+
+int sg_up2_fwd(const sg_view *x, const sg_view *y, void *hip_stream)
+{
+    if (!ok_view(x) || !ok_view(y) || !half_of(y, x)) return SG_EINVAL;
+    const int64_t n = (int64_t)y->n * y->d * y->h * y->w * y->c;
+    hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    return status();
+}
+
+int sg_up2_bwd(const sg_view *dy, const sg_view *dx, int32_t accumulate, void *hip_stream)
+{
+    if (!ok_view(dy) || !ok_view(dx) || !half_of(dy, dx)) return SG_EINVAL;
+    const int64_t n = (int64_t)dx->n * dx->d * dx->h * dx->w * dx->c;
+    hipLaunchKernelGGL(k_up2_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *dy, *dx, accumulate);
+    return status();
+}
+
+int sg_mse(const sg_view *out, const sg_view *target, const sg_view *grad, double *loss, void *hip_stream)
+{
+    if (!ok_view(out) || !ok_view(target) || !ok_view(grad) || !loss || !same_pos(out, target) ||
+        !same_pos(out, grad) || out->c != target->c || out->c != grad->c)
+        return SG_EINVAL;
+    const int nb = 256;
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, *out, *target, *grad, loss + 1);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(64), 0, (hipStream_t)hip_stream, (const double *)(loss + 1), nb, loss);
+    return status();
+}
+
+int sg_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2, float eps,
+            int64_t step, void *hip_stream)
+{
+    if (!w || !g || !m || !v || n <= 0 || step < 1) return SG_EINVAL;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, (double)step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, (double)step)));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, w, g, m, v, n, lr, beta1, beta2,
+                       eps, c1, c2);
+    return status();
+}
+
+int sg_pack(const float *f, int32_t nf, int32_t nx, int32_t ny, int32_t nz, int32_t x0, int32_t y0, int32_t z0,
+            const sg_view *y, const sg_view *y32, int32_t b, void *hip_stream)
+{
+    if (!f || !ok_view(y) || nf <= 0 || nf > y->c || b < 0 || b >= y->n || x0 < 0 || y0 < 0 || z0 < 0) return SG_EINVAL;
+    if (y32 && (!ok_view(y32) || !same_pos(y, y32))) return SG_EINVAL;
+    const sg_view none = {};
+    const int64_t n = (int64_t)y->d * y->h * y->w * y->c;
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, f, nf, nx, ny, nz, x0, y0, z0,
+                       *y, y32 ? *y32 : none, b);
+    return status();
+}
+
+int sg_unpack(const sg_view *x32, int32_t b, float *f, int32_t nf, void *hip_stream)
+{
+    if (!ok_view(x32) || !f || nf <= 0 || nf > x32->c || b < 0 || b >= x32->n) return SG_EINVAL;
+    const int64_t n = (int64_t)x32->d * x32->h * x32->w * nf;
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x32, b, f, nf);
+    return status();
+}
+
+int sg_lift(const float *rhoN, int64_t n, double rhoR_in, double rhoB_in, float *rhoR, float *rhoB, void *hip_stream)
+{
+    if (!rhoN || !rhoR || !rhoB || n <= 0) return SG_EINVAL;
+    hipLaunchKernelGGL(k_lift, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, rhoN, n, (float)rhoR_in,
+                       (float)rhoB_in, rhoR, rhoB);
+    return status();
+}
+
+}  // extern "C"

@@ -23,7 +23,7 @@ STORAGE = {"fp32": LBCG_FP32, "fp16s": LBCG_FP16S, "bf16s": LBCG_BF16S}
 # Every symbol include/lbcg.h declares.
 EXPORTS = ("lbcg_init", "lbcg_step", "lbcg_moments", "lbcg_free", "lbcg_last_error",
            "lbcg_steps_done", "lbcg_index_map", "lbcg_get_populations", "lbcg_case_nodes",
-           "lbcg_storage_bytes", "lbcg_timing", "lbcg_timing_read")
+           "lbcg_storage_bytes", "lbcg_timing", "lbcg_timing_read", "lbcg_set_fields")
 
 
 class LbcgError(RuntimeError):
@@ -96,6 +96,8 @@ def load():
     L.lbcg_timing.restype = C.c_int
     L.lbcg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.lbcg_timing_read.restype = C.c_int
+    L.lbcg_set_fields.argtypes = [vp, i32, C.POINTER(lbcg_fields)]
+    L.lbcg_set_fields.restype = C.c_int
     _lib = L
     return L
 
@@ -186,6 +188,19 @@ def lbcg_case_nodes(h, case_id):
 
 def lbcg_storage_bytes(h):
     return int(load().lbcg_storage_bytes(C.c_void_p(h)))
+
+
+def lbcg_set_fields(h, case_id, rhoR, rhoB, ux, uy, uz):
+    """Reset a case to equilibrium from device (torch CUDA float64) fields."""
+    f = lbcg_fields()
+    keep = [t.contiguous() for t in (rhoR, rhoB, ux, uy, uz)]
+    N = lbcg_case_nodes(h, case_id)
+    for t in keep:
+        if t.numel() != N or str(t.dtype) != "torch.float64" or not t.is_cuda:
+            raise ValueError("fields must be CUDA float64 tensors of the case's node count")
+    f.rhoR, f.rhoB, f.ux, f.uy, f.uz = [t.data_ptr() for t in keep]
+    f.on_device = 1
+    return _check(load().lbcg_set_fields(C.c_void_p(h), int(case_id), C.byref(f)))
 
 
 def lbcg_timing(h, enable):
