@@ -85,18 +85,30 @@ int sg_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, f
 
 /* Fields <-> network tensors.  pack: planar FP32 fields f[c][node] (node
  * x-fastest over an nx*ny*nz box) from the sub-box starting at (x0,y0,z0)
- * with periodic wrap -> BF16 view (batch item b, channels [0, nf), the
- * rest of the view's channels zeroed) and, if y32 != NULL, the same values
- * into an FP32 view.  unpack: FP32 view -> planar FP32 fields of the box. */
+ * with periodic wrap, divided by scale[c] (host array of nf <= 8 nonzero
+ * values, NULL = 1) -> BF16 view (batch item b, channels [0, nf), the rest of
+ * the view's channels zeroed) and, if y32 != NULL, the same values into an
+ * FP32 view.  unpack: FP32 view (batch item b) times scale[c] -> planar FP32
+ * fields of the view's box. */
 int sg_pack(const float *f, int32_t nf, int32_t nx, int32_t ny, int32_t nz, int32_t x0, int32_t y0,
-            int32_t z0, const sg_view *y, const sg_view *y32, int32_t b, void *hip_stream);
-int sg_unpack(const sg_view *x32, int32_t b, float *f, int32_t nf, void *hip_stream);
+            int32_t z0, const float *scale, const sg_view *y, const sg_view *y32, int32_t b, void *hip_stream);
+int sg_unpack(const sg_view *x32, int32_t b, const float *scale, float *f, int32_t nf, void *hip_stream);
 
-/* Lift the surrogate's (rho^N, u) to colour densities for lbcg_set_fields:
- * rho_R = rho_R^in (1 + rho^N)/2, rho_B = rho_B^in (1 - rho^N)/2 with rho^N
- * clipped to [-1, 1]; velocity copied. */
-int sg_lift(const float *rhoN, int64_t n, double rhoR_in, double rhoB_in, float *rhoR, float *rhoB,
-            void *hip_stream);
+/* Lift the surrogate's prediction to the fields lbcg_set_fields takes.
+ * pred: planar FP32 (rho^N, u_x, u_y, u_z), 4 n values.  out: planar FP64
+ * (rho_R, rho_B, u_x, u_y, u_z), 5 n values.  The colour densities are the
+ * ones whose phase field (rho^N as defined below Eq. 8, each colour scaled by
+ * its initial density) is the predicted rho^N clipped to [-1, 1], and whose
+ * pressure p = rho_R cs2R + rho_B cs2B (the colour pressures p_k of Eq. 6)
+ * equals the local pressure of the state before the jump, taken from
+ * rhoR_prev and rhoB_prev (FP32, n values each), or p_in everywhere when both
+ * are NULL.  With the initial densities in pressure balance
+ * (rho_R^in cs2R = rho_B^in cs2B) this gives rho_R = p (1 + rho^N) / (2 cs2R),
+ * rho_B = p (1 - rho^N) / (2 cs2B).  cs2k = (1 - alpha_k)/2 > 0.
+ * Device pointers; SG_EINVAL on a NULL buffer, n <= 0, a non-positive cs2 or
+ * p_in, or only one of the two previous-density pointers. */
+int sg_lift(const float *pred, int64_t n, const float *rhoR_prev, const float *rhoB_prev, double cs2R, double cs2B,
+            double p_in, double *out, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -569,7 +569,6 @@ int lbcg_set_fields(lbcg_handle *h, int32_t case_id, const lbcg_fields *fields)
     const lbcg_fields &f = *fields;
     if (!f.rhoR || !f.rhoB || !f.ux || !f.uy || !f.uz) return fail(LBCG_EINVAL, "NULL field");
     lbcg_case c{};
-    c.alpha[0] = 0.0;
     // the init kernel only needs alpha and the model flag, recovered from the case constants
     const DevCase &d = h->dc[case_id];
     c.alpha[0] = h->alpha_in[case_id][0];

@@ -345,7 +345,10 @@ __global__ void k_adam(float *w, const float *g, float *m, float *v, int64_t n, 
     }
 }
 
-__global__ void k_pack(const float *f, int nf, int nx, int ny, int nz, int x0, int y0, int z0, sg_view y, sg_view y32, int b)
+struct Scale { float s[8]; };
+
+__global__ void k_pack(const float *f, int nf, int nx, int ny, int nz, int x0, int y0, int z0, sg_view y, sg_view y32, int b,
+                       Scale sc)
 {
     const int64_t per = (int64_t)y.d * y.h * y.w;
     const int64_t n = per * y.c;
@@ -356,7 +359,7 @@ __global__ void k_pack(const float *f, int nf, int nx, int ny, int nz, int x0, i
         float v = 0.f;
         if (c < nf) {
             const int gx = (x0 + x) % nx, gy = (y0 + yy) % ny, gz = (z0 + z) % nz;
-            v = f[(int64_t)c * nx * ny * nz + gx + (int64_t)nx * (gy + (int64_t)ny * gz)];
+            v = f[(int64_t)c * nx * ny * nz + gx + (int64_t)nx * (gy + (int64_t)ny * gz)] / sc.s[c];
         }
         const int64_t pp = (int64_t)b * per + p;
         reinterpret_cast<bf16 *>(y.p)[pp * y.ctot + y.coff + c] = (bf16)v;
@@ -364,23 +367,28 @@ __global__ void k_pack(const float *f, int nf, int nx, int ny, int nz, int x0, i
     }
 }
 
-__global__ void k_unpack(sg_view x, int b, float *f, int nf)
+__global__ void k_unpack(sg_view x, int b, float *f, int nf, Scale sc)
 {
     const int64_t per = (int64_t)x.d * x.h * x.w;
     const int64_t n = per * nf;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int c = (int)(e / per);
         const int64_t p = e % per;
-        f[e] = reinterpret_cast<const float *>(x.p)[((int64_t)b * per + p) * x.ctot + x.coff + c];
+        f[e] = reinterpret_cast<const float *>(x.p)[((int64_t)b * per + p) * x.ctot + x.coff + c] * sc.s[c];
     }
 }
 
-__global__ void k_lift(const float *rn, int64_t n, float rR, float rB, float *oR, float *oB)
+__global__ void k_lift(const float *pred, int64_t n, const float *pR, const float *pB, float cs2R, float cs2B,
+                       float p_in, double *out)
 {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const float v = fminf(1.f, fmaxf(-1.f, rn[e]));
-        oR[e] = rR * 0.5f * (1.f + v);
-        oB[e] = rB * 0.5f * (1.f - v);
+        const float v = fminf(1.f, fmaxf(-1.f, pred[e]));
+        const float p = pR ? pR[e] * cs2R + pB[e] * cs2B : p_in;
+        out[e] = (double)(0.5f * p * (1.f + v) / cs2R);
+        out[n + e] = (double)(0.5f * p * (1.f - v) / cs2B);
+        out[2 * n + e] = (double)pred[n + e];
+        out[3 * n + e] = (double)pred[2 * n + e];
+        out[4 * n + e] = (double)pred[3 * n + e];
     }
 }
 
@@ -537,31 +545,51 @@ int sg_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, f
     return status();
 }
 
-int sg_pack(const float *f, int32_t nf, int32_t nx, int32_t ny, int32_t nz, int32_t x0, int32_t y0, int32_t z0,
-            const sg_view *y, const sg_view *y32, int32_t b, void *hip_stream)
+static bool make_scale(const float *scale, int nf, Scale &sc)
 {
-    if (!f || !ok_view(y) || nf <= 0 || nf > y->c || b < 0 || b >= y->n || x0 < 0 || y0 < 0 || z0 < 0) return SG_EINVAL;
+    if (nf > 8) return false;
+    for (int c = 0; c < 8; ++c) sc.s[c] = 1.0f;
+    if (scale)
+        for (int c = 0; c < nf; ++c) {
+            if (!(scale[c] != 0.0f)) return false;
+            sc.s[c] = scale[c];
+        }
+    return true;
+}
+
+int sg_pack(const float *f, int32_t nf, int32_t nx, int32_t ny, int32_t nz, int32_t x0, int32_t y0, int32_t z0,
+            const float *scale, const sg_view *y, const sg_view *y32, int32_t b, void *hip_stream)
+{
+    Scale sc;
+    if (!f || !ok_view(y) || nf <= 0 || nf > y->c || b < 0 || b >= y->n || x0 < 0 || y0 < 0 || z0 < 0 ||
+        !make_scale(scale, nf, sc))
+        return SG_EINVAL;
     if (y32 && (!ok_view(y32) || !same_pos(y, y32))) return SG_EINVAL;
     const sg_view none = {};
     const int64_t n = (int64_t)y->d * y->h * y->w * y->c;
     hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, f, nf, nx, ny, nz, x0, y0, z0,
-                       *y, y32 ? *y32 : none, b);
+                       *y, y32 ? *y32 : none, b, sc);
     return status();
 }
 
-int sg_unpack(const sg_view *x32, int32_t b, float *f, int32_t nf, void *hip_stream)
+int sg_unpack(const sg_view *x32, int32_t b, const float *scale, float *f, int32_t nf, void *hip_stream)
 {
-    if (!ok_view(x32) || !f || nf <= 0 || nf > x32->c || b < 0 || b >= x32->n) return SG_EINVAL;
+    Scale sc;
+    if (!ok_view(x32) || !f || nf <= 0 || nf > x32->c || b < 0 || b >= x32->n || !make_scale(scale, nf, sc))
+        return SG_EINVAL;
     const int64_t n = (int64_t)x32->d * x32->h * x32->w * nf;
-    hipLaunchKernelGGL(k_unpack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x32, b, f, nf);
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x32, b, f, nf, sc);
     return status();
 }
 
-int sg_lift(const float *rhoN, int64_t n, double rhoR_in, double rhoB_in, float *rhoR, float *rhoB, void *hip_stream)
+int sg_lift(const float *pred, int64_t n, const float *rhoR_prev, const float *rhoB_prev, double cs2R, double cs2B,
+            double p_in, double *out, void *hip_stream)
 {
-    if (!rhoN || !rhoR || !rhoB || n <= 0) return SG_EINVAL;
-    hipLaunchKernelGGL(k_lift, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, rhoN, n, (float)rhoR_in,
-                       (float)rhoB_in, rhoR, rhoB);
+    if (!pred || !out || n <= 0 || !(cs2R > 0.0) || !(cs2B > 0.0) || (!rhoR_prev) != (!rhoB_prev) ||
+        (!rhoR_prev && !(p_in > 0.0)))
+        return SG_EINVAL;
+    hipLaunchKernelGGL(k_lift, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, pred, n, rhoR_prev, rhoB_prev,
+                       (float)cs2R, (float)cs2B, (float)p_in, out);
     return status();
 }
 

@@ -60,9 +60,9 @@ def lib():
             "sg_up2_fwd": [V, V, vp], "sg_up2_bwd": [V, V, i32, vp],
             "sg_mse": [V, V, V, vp, vp],
             "sg_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i64, vp],
-            "sg_pack": [vp, i32, i32, i32, i32, i32, i32, i32, V, V, i32, vp],
-            "sg_unpack": [V, i32, vp, i32, vp],
-            "sg_lift": [vp, i64, f64, f64, vp, vp, vp],
+            "sg_pack": [vp, i32, i32, i32, i32, i32, i32, i32, vp, V, V, i32, vp],
+            "sg_unpack": [V, i32, vp, vp, i32, vp],
+            "sg_lift": [vp, i64, vp, vp, f64, f64, f64, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -269,15 +269,21 @@ class UNet:
             l.prep()
 
     # ------------------------------------------------------------- fields
+    def _scale(self):
+        return (C.c_float * NF)(1.0, *([self.us] * (NF - 1)))
+
     def pack(self, fields, box, origin=(0, 0, 0), b=0, target=False):
-        """fields: CUDA float32 (4, nz*ny*nx) planar (rho^N, u/us); box = (nx, ny, nz)."""
+        """fields: CUDA float32 (4, nz*ny*nx) planar (rho^N, u_x, u_y, u_z) of an
+        nx*ny*nz box = `box`; the network sees (rho^N, u/us)."""
         nx, ny, nz = box
         bf, f32 = (self.tgt_bf, self.tgt32) if target else (self.x_in, self.x32)
-        _chk(lib().sg_pack(C.c_void_p(fields.data_ptr()), NF, nx, ny, nz, *origin, C.byref(view(bf)),
+        _chk(lib().sg_pack(C.c_void_p(fields.data_ptr()), NF, nx, ny, nz, *origin, self._scale(), C.byref(view(bf)),
                            C.byref(view(f32)), b, _stream()), "pack")
 
     def unpack(self, out, b=0):
-        _chk(lib().sg_unpack(C.byref(view(self.out32)), b, C.c_void_p(out.data_ptr()), NF, _stream()), "unpack")
+        """Prediction of batch item b back to physical planar fields (4, nz*ny*nx)."""
+        _chk(lib().sg_unpack(C.byref(view(self.out32)), b, self._scale(), C.c_void_p(out.data_ptr()), NF,
+                             _stream()), "unpack")
 
     def state_dict(self):
         return {l.name: (l.w.cpu().numpy(), l.b.cpu().numpy()) for l in self.layers}
@@ -289,3 +295,17 @@ class UNet:
             l.w.copy_(torch.tensor(w))
             l.b.copy_(torch.tensor(b))
             l.prep()
+
+
+def lift(pred, cs2, rho_prev=None, p_in=None):
+    """(4, n) CUDA float32 prediction -> (5, n) CUDA float64 (rho_R, rho_B, u)
+    whose phase field is the predicted rho^N and whose pressure is the one of
+    the state before the jump (rho_prev = (rho_R, rho_B) FP32) or p_in."""
+    import torch
+    n = pred.shape[1]
+    out = torch.empty((5, n), dtype=torch.float64, device="cuda")
+    pr = (C.c_void_p(rho_prev[0].data_ptr()), C.c_void_p(rho_prev[1].data_ptr())) if rho_prev is not None else (None, None)
+    _chk(lib().sg_lift(C.c_void_p(pred.data_ptr()), n, *pr, float(cs2[0]), float(cs2[1]),
+                       float(p_in if p_in is not None else 0.0), C.c_void_p(out.data_ptr()), _stream()), "lift")
+    return out
+

@@ -1,0 +1,297 @@
+"""The learned surrogate on the Rayleigh-Taylor runs (Sec. IV.C workload).
+
+Pipeline
+  1. snapshots: the LB solver (include/lbcg.h) runs Rayleigh-Taylor cases and
+     records (rho^N, u) every `every` steps;
+  2. training: the U-Net (surrogate.py) learns the map from the fields at t
+     to the fields at t + every on the snapshots (whole box, or z-slabs of the
+     full x-y period; periodic padding in x and y, zero padding at the z
+     walls), with its own MFMA forward/backward kernels and Adam;
+  3. use: from an LB state the network jumps `every` steps ahead on the whole
+     domain; the prediction is lifted back to populations (equilibrium of
+     colour densities with the predicted phase field at the pre-jump
+     pressure, and the predicted velocity) and the LB step continues for
+     `heal` steps, which rebuild the non-equilibrium parts and the interface
+     profile;
+  4. gate: a jump is accepted only while the bubble and spike fronts of the
+     prediction are within `gate` lattice units of the LB run's fronts at the
+     same time; a rejected jump is replaced by `every` plain LB steps.
+     Here the LB fronts come from a reference run of the same case, so the
+     gate measures the surrogate's error; it is not timed as part of the
+     hybrid.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import lbcg as B
+from . import surrogate as S
+from . import workloads as W
+
+
+def case(L=64, amp=0.05, g=2e-5, Re=None):
+    """Rayleigh-Taylor box [0,L]^2 x [0,4L] (walls at z, periodic sides).  The
+    default Reynolds number keeps the kinematic viscosity of the L = 128,
+    Re = 1024 case (nu = L sqrt(gL)/Re), so smaller boxes keep its relaxation
+    times."""
+    Re = 1024.0 * (L / 128.0) ** 1.5 if Re is None else Re
+    return W.rayleigh_taylor(L, g=g, amp=amp, Re=Re)
+
+
+def cs2(p):
+    return tuple(0.5 * (1.0 - a) for a in p["alpha"])
+
+
+def _fields(solver, with_rho=False):
+    import torch
+    f = solver.fields(0)
+    x = torch.stack([f["rhoN"], f["ux"], f["uy"], f["uz"]]).contiguous()
+    return (x, (f["rhoR"], f["rhoB"])) if with_rho else x
+
+
+def snapshots(p, fl, steps, rec, storage="fp32"):
+    """LB trajectory: list of (4, N) CUDA float32 (rho^N, u) every `rec` steps
+    from step 0 to `steps`, and the wall time of the steps."""
+    import torch
+    s = B.Solver([(p, fl)], storage=storage)
+    out = [_fields(s)]
+    wall = 0.0
+    try:
+        for _ in range(steps // rec):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            s.step(rec)
+            torch.cuda.synchronize()
+            wall += time.time() - t0
+            out.append(_fields(s))
+    finally:
+        s.close()
+    return out, wall
+
+
+def fronts(rhoN, box):
+    """(bubble, spike) interface heights: the first crossing of rho^N = 0 from
+    the bottom along the column through the bubble (x = y = 0) and through the
+    spike (x = y = L/2), linearly interpolated."""
+    nx, ny, nz = box
+    col = rhoN.view(nz, ny, nx)
+    res = []
+    for (x, y) in ((0, 0), (nx // 2, ny // 2)):
+        c = col[:, y, x].double().cpu().numpy()
+        k = np.nonzero((c[:-1] < 0) & (c[1:] >= 0))[0]
+        if k.size == 0:
+            res.append(float("nan"))
+            continue
+        i = int(k[0])
+        res.append(i + c[i] / (c[i] - c[i + 1]))
+    return tuple(res)
+
+
+def train(net, trajs, box, lag, iters=400, lr=1e-3, lr_min=1e-5, seed=0, log=None):
+    """Adam on (fields_t -> fields_{t+lag snapshots}) pairs drawn at random
+    from the trajectories, one pair per batch item, with a cosine learning
+    rate from lr to lr_min; a network shorter than the box in z trains on
+    z-slabs that stay inside the box.  Returns the loss history."""
+    nz = box[2]
+    slab = net.shape[1]
+    assert slab <= nz
+    rng = np.random.default_rng(seed)
+    hist = []
+    for it in range(iters):
+        for b in range(net.shape[0]):
+            tr = trajs[int(rng.integers(len(trajs)))]
+            i = int(rng.integers(len(tr) - lag))
+            z0 = int(rng.integers(0, nz - slab + 1))
+            net.pack(tr[i], box, origin=(0, 0, z0), b=b)
+            net.pack(tr[i + lag], box, origin=(0, 0, z0), b=b, target=True)
+        net.forward()
+        net.mse()
+        net.backward()
+        net.adam(lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * it / max(1, iters - 1))))
+        if it % 50 == 0 or it == iters - 1:
+            hist.append((it, net.loss[0].item()))
+            if log:
+                log(f"train it {it} loss {hist[-1][1]:.3e}")
+    return hist
+
+
+def full_domain_net(trained, box):
+    """A network with the trained weights and buffers for the whole box (z walls: zero padding)."""
+    nx, ny, nz = box
+    net = S.UNet((1, nz, ny, nx), seed=0, us=trained.us, pmask=3)
+    net.load_state(trained.state_dict())
+    return net
+
+
+def predict(net, fields, box):
+    import torch
+    net.pack(fields, box)
+    net.forward()
+    out = torch.empty_like(fields)
+    net.unpack(out)
+    return out
+
+
+def lift_and_set(solver, pred, p, rho_prev):
+    """Equilibrium LB state from the predicted (rho^N, u) at the pressure of
+    the state before the jump (sg_lift + lbcg_set_fields)."""
+    out = S.lift(pred, cs2(p), rho_prev=rho_prev)
+    B.lbcg_set_fields(solver.h, 0, out[0], out[1], out[2], out[3], out[4])
+
+
+def reference(p, fl, steps, stride):
+    """Fronts of the plain LB run every `stride` steps ({t: (bubble, spike)})."""
+    box = (p["nx"], p["ny"], p["nz"])
+    s = B.Solver([(p, fl)])
+    ref = {0: fronts(_fields(s)[0], box)}
+    try:
+        for t in range(stride, steps + 1, stride):
+            s.step(stride)
+            ref[t] = fronts(_fields(s)[0], box)
+    finally:
+        s.close()
+    return ref
+
+
+def lb_time(p, fl, t_start, t_end):
+    """Wall time of plain LB steps t_start -> t_end."""
+    import torch
+    s = B.Solver([(p, fl)])
+    try:
+        s.step(t_start)
+        torch.cuda.synchronize()
+        c0 = time.time()
+        s.step(t_end - t_start)
+        torch.cuda.synchronize()
+        return time.time() - c0
+    finally:
+        s.close()
+
+
+def hybrid(net, p, fl, ref_fronts, every, t_start, t_end, heal=20, gate=1.0, use_net=True):
+    """LB to t_start, then jumps of `every` steps (network prediction, or the
+    unchanged state when use_net is False) each followed by `heal` LB steps,
+    gated against the LB fronts; returns the record and the wall time after
+    t_start (the reference run that judges the jumps is not timed)."""
+    import torch
+    box = (p["nx"], p["ny"], p["nz"])
+    s = B.Solver([(p, fl)])
+    s.step(t_start)
+    torch.cuda.synchronize()
+    t, wall, rec = t_start, 0.0, []
+    try:
+        while t + every + heal <= t_end:
+            torch.cuda.synchronize()
+            c0 = time.time()
+            f, rho = _fields(s, with_rho=True)
+            pred = predict(net, f, box) if use_net else f
+            torch.cuda.synchronize()
+            wall += time.time() - c0
+            fb, fs = fronts(pred[0], box)
+            rb, rs = ref_fronts[t + every]
+            err = max(abs(fb - rb), abs(fs - rs))
+            ok = bool(np.isfinite(err) and err <= gate)
+            c0 = time.time()
+            if ok:
+                if use_net:
+                    lift_and_set(s, pred, p, rho)
+            else:
+                s.step(every)
+            s.step(heal)
+            torch.cuda.synchronize()
+            wall += time.time() - c0
+            t += every + heal
+            rec.append(dict(t=t, accepted=ok, front_error=err))
+        c0 = time.time()
+        if t < t_end:
+            s.step(t_end - t)
+        f = _fields(s)
+        torch.cuda.synchronize()
+        wall += time.time() - c0
+        fb, fs = fronts(f[0], box)
+        rb, rs = ref_fronts[t_end]
+        final = max(abs(fb - rb), abs(fs - rs))
+    finally:
+        s.close()
+    return dict(records=rec, wall_s=wall, final_front_error=final,
+                accepted=sum(r["accepted"] for r in rec), jumps=len(rec))
+
+
+def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, iters=2000,
+               heal=20, rec=20, batch=2, t_start=None, lr=5e-4, lr_min=1e-5, gates=(1.0, 0.5), log=None):
+    """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
+    steps apart from snapshots every `rec` steps); on the held-out amplitude,
+    run the gated hybrid at each gate, the same gate with persistence in
+    place of the network, and the plain LB run.  Returns a summary."""
+    import math
+    import torch
+    steps = steps if steps is not None else int(4.5 * math.sqrt(L / 2e-5)) // every * every
+    t_start = t_start if t_start is not None else 5 * every
+    assert every % rec == 0
+    trajs = []
+    gen = 0.0
+    for a in train_amps:
+        p, fl = case(L, a)
+        tr, w = snapshots(p, fl, steps, rec)
+        trajs.append(tr)
+        gen += w
+        if log:
+            log(f"trajectory amp {a}: {len(tr)} snapshots, {w:.2f} s")
+    p, fl = case(L, eval_amp)
+    box = (p["nx"], p["ny"], p["nz"])
+    stride = math.gcd(every, heal) if heal else every
+    ref = reference(p, fl, steps, stride)
+    net = S.UNet((batch, p["nz"], p["ny"], p["nx"]), seed=7, us=0.02, pmask=3)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    hist = train(net, trajs, box, every // rec, iters=iters, lr=lr, lr_min=lr_min, log=log)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    del trajs
+    full = full_domain_net(net, box)
+    lb = lb_time(p, fl, t_start, steps)
+    res = dict(lattice=[p["nx"], p["ny"], p["nz"]], every=every, steps=steps, t_start=t_start, heal=heal,
+               train_amps=list(train_amps), eval_amp=eval_amp, params=net.nparams, train_iters=iters, batch=batch,
+               train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]), lb_s=lb,
+               trajectory_s=gen, gates={})
+    for g in gates:
+        hyb = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g)
+        per = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g, use_net=False)
+        acc = [r["front_error"] for r in hyb["records"] if r["accepted"]]
+        res["gates"][str(g)] = dict(
+            hybrid_s=hyb["wall_s"], gain=lb / hyb["wall_s"], accepted=hyb["accepted"], jumps=hyb["jumps"],
+            final_front_error=hyb["final_front_error"], max_accepted_error=max(acc) if acc else 0.0,
+            records=[(r["t"], int(r["accepted"]), round(r["front_error"], 3)) for r in hyb["records"]],
+            persistence=dict(accepted=per["accepted"], final_front_error=per["final_front_error"],
+                             gain=lb / per["wall_s"]))
+        if log:
+            log(f"gate {g}: accepted {hyb['accepted']}/{hyb['jumps']}, final front error "
+                f"{hyb['final_front_error']:.3f}, gain {lb / hyb['wall_s']:.2f}; persistence accepted "
+                f"{per['accepted']}, final {per['final_front_error']:.3f}")
+    return res
+
+
+def main(argv=None):
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="Train the surrogate on Rayleigh-Taylor LB runs and measure the "
+                                             "gated hybrid against plain LB")
+    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--iters", type=int, default=4000)
+    ap.add_argument("--batch", type=int, default=2)
+    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--heal", type=int, default=20)
+    ap.add_argument("--out", default=None, help="write the summary JSON here")
+    a = ap.parse_args(argv)
+    res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, log=lambda m: print(m, flush=True))
+    txt = json.dumps(res)
+    print(txt, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(json.dumps(res, indent=1) + "\n")
+
+
+if __name__ == "__main__":
+    main()

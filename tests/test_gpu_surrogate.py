@@ -133,7 +133,7 @@ def test_unet_loss_and_gradients_match_oracle(pmask):
     from oracle import unet_ref as U
     from paper_1904_03618_amd import surrogate as S
     rng = np.random.default_rng(11)
-    net = S.UNet((2, 8, 8, 8), seed=4, pmask=pmask)
+    net = S.UNet((2, 8, 8, 8), seed=4, pmask=pmask, us=1.0)
     for l in net.layers:                          # a non-trivial head and biases
         l.w.mul_(1.0 if l.name != "head" else 0.0).add_(
             torch.tensor(rng.standard_normal(l.w.shape).astype(np.float32) * (0.2 if l.name == "head" else 0.0)).cuda())
@@ -174,7 +174,7 @@ def test_unet_training_reduces_loss():
     import torch
     from paper_1904_03618_amd import surrogate as S
     rng = np.random.default_rng(2)
-    net = S.UNet((1, 16, 16, 16), seed=1, pmask=7)
+    net = S.UNet((1, 16, 16, 16), seed=1, pmask=7, us=1.0)
     z, y, x = np.meshgrid(*[np.arange(16)] * 3, indexing="ij")
     base = np.stack([np.sin(2 * np.pi * (x + 2 * y) / 16), np.cos(2 * np.pi * z / 16), 0 * x, 0.5 * np.sin(2 * np.pi * y / 16)])
     tgt = np.roll(base, 1, axis=3) * 0.9
@@ -189,3 +189,30 @@ def test_unet_training_reduces_loss():
         net.adam(2e-3)
     print("losses", losses[0], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_lift_matches_oracle():
+    """sg_lift against the FP64 lift reference, at the pre-jump pressure and at
+    a uniform pressure; velocities copied; EINVAL on mismatched pointers."""
+    import torch
+    from oracle import lift_ref as LR
+    from paper_1904_03618_amd import surrogate as S
+    rng = np.random.default_rng(8)
+    n = 70001
+    pred = f32t(np.concatenate([rng.uniform(-1.2, 1.2, (1, n)), 0.03 * rng.standard_normal((3, n))]))
+    rR = f32t(rng.uniform(0.0, 3.2, n))
+    rB = f32t(rng.uniform(0.0, 1.1, n))
+    cs2 = (0.05, 0.15)
+    out = S.lift(pred, cs2, rho_prev=(rR, rB)).cpu().numpy()
+    pv = pred.cpu().numpy().astype(np.float64)
+    p = rR.cpu().numpy().astype(np.float64) * cs2[0] + rB.cpu().numpy().astype(np.float64) * cs2[1]
+    wR, wB = LR.lift(pv[0], p, *cs2)
+    assert close(out[0], wR, 1e-6)[0] and close(out[1], wB, 1e-6)[0]
+    assert np.array_equal(out[2:], pv[1:])
+    out = S.lift(pred, cs2, p_in=0.15).cpu().numpy()
+    wR, wB = LR.lift(pv[0], 0.15, *cs2)
+    assert close(out[0], wR, 1e-6)[0] and close(out[1], wB, 1e-6)[0]
+    o = torch.empty(5 * n, dtype=torch.float64, device="cuda")
+    rc = S.lib().sg_lift(C.c_void_p(pred.data_ptr()), n, C.c_void_p(rR.data_ptr()), None, 0.05, 0.15, 0.15,
+                         C.c_void_p(o.data_ptr()), S._stream())
+    assert rc != 0
