@@ -71,9 +71,14 @@ __device__ inline void tap_offset(int tap, int k, int &dz, int &dy, int &dx)
 }
 
 // ------------------------------------------------------------- forward
-// Workgroup: 4 wavefronts, each a 16 (output channels) x 16 (positions) tile;
-// blockIdx.y selects the 16 output channels.  The K loop walks taps x input
-// channels in groups of 8 (one 16-byte load per lane and operand).
+// Workgroup: 4 wavefronts; each wave owns a register tile of NO blocks of 16
+// output channels x FP blocks of 16 positions (64 consecutive positions), so
+// one weight fragment feeds FP MFMAs and one input fragment feeds NO of them.
+// blockIdx.y selects the 16 NO output channels.  The K loop walks taps x
+// input channels in groups of 8 (one 16-byte load per lane and operand).
+constexpr int FP = 4;
+
+template <int NO>
 __global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restrict__ W,
                                                   const float *__restrict__ bias, int k, int pmask, int relu,
                                                   sg_view y, sg_view y32, int accumulate)
@@ -81,50 +86,78 @@ __global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restr
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
     const int64_t P = npos(x);
-    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * 16;
-    const int co0 = blockIdx.y * 16;
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * FP);
+    const int co0 = blockIdx.y * 16 * NO;
     const int ci = x.c, g8 = ci >> 3, taps = k * k * k;
     const int K8 = taps * g8, K = taps * ci;
-    const int64_t pb = p0 + col;
-    const bool pvalid = pb < P;
-    const Pos q = decode(x, pvalid ? pb : 0);
-    const bf16 *xp = reinterpret_cast<const bf16 *>(x.p);
+    Pos q[FP];
+    bool pv[FP];
+    #pragma unroll
+    for (int i = 0; i < FP; ++i) {
+        const int64_t pb = p0 + 16 * i + col;
+        pv[i] = pb < P;
+        q[i] = decode(x, pv[i] ? pb : 0);
+    }
+    const bf16 *xp = reinterpret_cast<const bf16 *>(x.p) + x.coff;
     const bf16 *wrow = W + (int64_t)(co0 + col) * K;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[NO][FP];
+    #pragma unroll
+    for (int o = 0; o < NO; ++o)
+        #pragma unroll
+        for (int i = 0; i < FP; ++i) acc[o][i] = f32x4{0.f, 0.f, 0.f, 0.f};
     const bf16x8 zero = {};
     int last_tap = -1;
-    int64_t src = -1;
+    int64_t src[FP];
+    #pragma unroll
+    for (int i = 0; i < FP; ++i) src[i] = -1;
     for (int kb = 0; kb < (K8 + 3) >> 2; ++kb) {
         const int g = (kb << 2) + grp;
-        bf16x8 a = zero, b = zero;
+        bf16x8 a[NO], b[FP];
+        #pragma unroll
+        for (int o = 0; o < NO; ++o) a[o] = zero;
+        #pragma unroll
+        for (int i = 0; i < FP; ++i) b[i] = zero;
         if (g < K8) {
             const int tap = g / g8, c8 = g - tap * g8;
-            a = *reinterpret_cast<const bf16x8 *>(wrow + (g << 3));
+            #pragma unroll
+            for (int o = 0; o < NO; ++o) a[o] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * o * K + (g << 3));
             if (tap != last_tap) {
                 int dz, dy, dx;
                 tap_offset(tap, k, dz, dy, dx);
-                src = pvalid ? shifted(x, q, dz, dy, dx, pmask) : -1;
+                #pragma unroll
+                for (int i = 0; i < FP; ++i) src[i] = pv[i] ? shifted(x, q[i], dz, dy, dx, pmask) : -1;
                 last_tap = tap;
             }
-            if (src >= 0) b = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + (c8 << 3));
+            #pragma unroll
+            for (int i = 0; i < FP; ++i)
+                if (src[i] >= 0) b[i] = *reinterpret_cast<const bf16x8 *>(xp + src[i] * x.ctot + (c8 << 3));
         }
-        acc = mfma(a, b, acc);
+        #pragma unroll
+        for (int o = 0; o < NO; ++o)
+            #pragma unroll
+            for (int i = 0; i < FP; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
     }
-    if (!pvalid) return;
     #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int oc = co0 + (grp << 2) + j;
-        const bool sy = y.p && oc < y.c, s32 = y32.p && oc < y32.c;
-        if (!sy && !s32) continue;                 // padded output rows
-        float v = acc[j] + (bias ? bias[oc] : 0.f);
-        if (relu) v = fmaxf(v, 0.f);
-        if (sy)
-            reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc] = (bf16)v;
-        if (s32) {
-            float *o = reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc;
-            *o = accumulate ? *o + v : v;
+    for (int o = 0; o < NO; ++o)
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int oc = co0 + 16 * o + (grp << 2) + j;
+            const bool sy = y.p && oc < y.c, s32 = y32.p && oc < y32.c;
+            if (!sy && !s32) continue;                 // padded output rows
+            const float bo = bias ? bias[oc] : 0.f;
+            #pragma unroll
+            for (int i = 0; i < FP; ++i) {
+                if (!pv[i]) continue;
+                const int64_t pb = p0 + 16 * i + col;
+                float v = acc[o][i][j] + bo;
+                if (relu) v = fmaxf(v, 0.f);
+                if (sy) reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc] = (bf16)v;
+                if (s32) {
+                    float *out = reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc;
+                    *out = accumulate ? *out + v : v;
+                }
+            }
         }
-    }
 }
 
 // Master weights -> BF16 [co_pad][K] and the flipped transpose
@@ -148,49 +181,124 @@ __global__ void k_weight_prep(const float *w32, int co, int ci, int k, bf16 *wb,
 }
 
 // ------------------------------------------------------ weight gradient
-// D[co][kcol] += sum_p dy[p][co] x[p + tap(kcol)][c(kcol)] over one chunk of
-// positions; A = dy^T (16 co x 32 positions), B = shifted x (32 positions x
-// 16 K-columns).  Partial sums per chunk go to ws[chunk][co_pad][K].
-__global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k, int pmask, int chunk, int co_pad,
-                                                    float *ws)
+// dW[co][tap ci + c] = sum_p dy[p][co] x[p + off(tap)][c].  The contraction
+// runs over positions, which are not contiguous in the channels-last tensors,
+// so each workgroup stages a chunk of BPC positions in LDS transposed to
+// position-fastest rows: dy for its 16 NOB output channels and, for every tap,
+// the shifted x rows of its 16-channel input block.  The MFMA then reads
+// A = dy^T (16 co x 32 positions) and B = x (32 positions x 16 channels) as
+// 16-byte rows.  Wave w owns taps w, w + 4, ...; its accumulators stay in
+// registers over all chunks of its position group (grid.x), and each group
+// writes one partial sum per weight to ws[group][co_pad][K].
+constexpr int BPC = 64;              // positions per staged chunk
+constexpr int BROW = BPC + 8;        // LDS row length (bf16), padded against bank conflicts
+constexpr int BTAPS = 7;             // taps per wave (27 taps over 4 waves)
+
+template <int NOB>
+__global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k, int pmask, int groups, int co_pad,
+                                                    float *ws, float *wsb)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ __attribute__((aligned(16))) bf16 xs[27][16][BROW];
+    __shared__ __attribute__((aligned(16))) bf16 dyt[16 * NOB][BROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = lane & 15, grp = lane >> 4;
     const int ci = x.c, taps = k * k * k, K = taps * ci;
-    const int kc = (blockIdx.x * 4 + wave) * 16 + col;     // this lane's K-column (B operand)
-    const int co0 = blockIdx.y * 16;
-    const int co = co0 + col;                              // this lane's row (A operand)
+    const int co0 = blockIdx.y * 16 * NOB, c0 = blockIdx.z * 16;
     const int64_t P = npos(x);
-    const int64_t pbeg = (int64_t)blockIdx.z * chunk, pend = min(P, pbeg + chunk);
-    const bool kvalid = kc < K;
-    int tap = 0, c = 0, dz = 0, dyo = 0, dx = 0;
-    if (kvalid) {
-        tap = kc / ci;
-        c = kc - tap * ci;
-        tap_offset(tap, k, dz, dyo, dx);
-    }
+    const int64_t nchunks = (P + BPC - 1) / BPC;
     const bf16 *xp = reinterpret_cast<const bf16 *>(x.p);
     const bf16 *dp = reinterpret_cast<const bf16 *>(dy.p);
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t p0 = pbeg; p0 < pend; p0 += 32) {
-        bf16x8 a = {}, b = {};
+    const bf16x8 zero = {};
+    // staging roles: x rows: position tid/2 (of 128 lanes per tap parity), 8-channel half tid&1
+    const int xpos = (tid & 127) >> 1, xc8 = tid & 1, xtap0 = tid >> 7;
+    const bool xcv = c0 + 8 * xc8 < ci;
+    // dy rows: position tid / (2 NOB), 8-channel group tid % (2 NOB)
+    const int dpos = tid / (2 * NOB), dc8 = tid % (2 * NOB);
+    const int doc = co0 + 8 * dc8;
+    f32x4 acc[BTAPS][NOB], accb[NOB];
+    #pragma unroll
+    for (int t = 0; t < BTAPS; ++t)
         #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t p = p0 + (grp << 3) + j;
-            if (p < pend) {
-                if (co < dy.c) a[j] = dp[p * dy.ctot + dy.coff + co];
-                if (kvalid) {
-                    const int64_t s = shifted(x, decode(x, p), dz, dyo, dx, pmask);
-                    if (s >= 0) b[j] = xp[s * x.ctot + x.coff + c];
+        for (int o = 0; o < NOB; ++o) acc[t][o] = f32x4{0.f, 0.f, 0.f, 0.f};
+    #pragma unroll
+    for (int o = 0; o < NOB; ++o) accb[o] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // the bias gradient is the weight gradient of an input channel of ones;
+    // the wave with the fewest taps computes it in the first input-channel block
+    const bool bias_wave = wsb && blockIdx.z == 0 && wave == taps % 4;
+    bf16x8 ones;
+    #pragma unroll
+    for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
+
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += groups) {
+        const int64_t pbase = ch * BPC;
+        __syncthreads();                                   // previous chunk's MFMA reads are done
+        {
+            const int64_t p = pbase + xpos;
+            const bool pv = p < P;
+            const Pos q = decode(x, pv ? p : 0);
+            for (int t = xtap0; t < taps; t += 2) {
+                bf16x8 v = zero;
+                if (pv && xcv) {
+                    int dz, dyo, dx;
+                    tap_offset(t, k, dz, dyo, dx);
+                    const int64_t src = shifted(x, q, dz, dyo, dx, pmask);
+                    if (src >= 0) v = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + c0 + 8 * xc8);
                 }
+                #pragma unroll
+                for (int j = 0; j < 8; ++j) xs[t][8 * xc8 + j][xpos] = v[j];
             }
         }
-        acc = mfma(a, b, acc);
+        if (dpos < BPC) {
+            const int64_t p = pbase + dpos;
+            bf16x8 v = zero;
+            if (p < P && doc < dy.c) {
+                v = *reinterpret_cast<const bf16x8 *>(dp + p * dy.ctot + dy.coff + doc);
+                #pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (doc + j >= dy.c) v[j] = (bf16)0.f;
+            }
+            #pragma unroll
+            for (int j = 0; j < 8; ++j) dyt[8 * dc8 + j][dpos] = v[j];
+        }
+        __syncthreads();
+        #pragma unroll
+        for (int ks = 0; ks < BPC / 32; ++ks) {
+            bf16x8 a[NOB];
+            #pragma unroll
+            for (int o = 0; o < NOB; ++o) a[o] = *reinterpret_cast<const bf16x8 *>(&dyt[16 * o + col][32 * ks + 8 * grp]);
+            #pragma unroll
+            for (int ti = 0; ti < BTAPS; ++ti) {
+                const int t = wave + 4 * ti;
+                if (t < taps) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xs[t][col][32 * ks + 8 * grp]);
+                    #pragma unroll
+                    for (int o = 0; o < NOB; ++o) acc[ti][o] = mfma(a[o], b, acc[ti][o]);
+                }
+            }
+            if (bias_wave)
+                #pragma unroll
+                for (int o = 0; o < NOB; ++o) accb[o] = mfma(a[o], ones, accb[o]);
+        }
     }
+    if (bias_wave && col == 0)
+        #pragma unroll
+        for (int o = 0; o < NOB; ++o)
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) wsb[(int64_t)blockIdx.x * co_pad + co0 + 16 * o + 4 * grp + j] = accb[o][j];
+    // D[4 grp + j][col]: output channel co0 + 16 o + 4 grp + j, input channel c0 + col
+    const int c = c0 + col;
+    if (c >= ci) return;
     #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int oc = co0 + (grp << 2) + j;
-        if (kvalid) ws[((int64_t)blockIdx.z * co_pad + oc) * K + kc] = acc[j];
+    for (int ti = 0; ti < BTAPS; ++ti) {
+        const int t = wave + 4 * ti;
+        if (t >= taps) continue;
+        #pragma unroll
+        for (int o = 0; o < NOB; ++o)
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int oc = co0 + 16 * o + 4 * grp + j;
+                ws[((int64_t)blockIdx.x * co_pad + oc) * K + (int64_t)t * ci + c] = acc[ti][o][j];
+            }
     }
 }
 
@@ -203,24 +311,6 @@ __global__ void k_reduce_chunks(const float *ws, int nchunks, int co_pad, int co
         for (int ch = 0; ch < nchunks; ++ch) s += ws[((int64_t)ch * co_pad + o) * K + kc];
         dw[e] = s;
     }
-}
-
-// db[co] = sum_p dy[p][co]: one workgroup per channel, fixed-order tree.
-__global__ __launch_bounds__(256) void k_bias_grad(sg_view dy, float *db)
-{
-    __shared__ float sh[256];
-    const int oc = blockIdx.x;
-    const int64_t P = npos(dy);
-    const bf16 *dp = reinterpret_cast<const bf16 *>(dy.p);
-    float s = 0.f;
-    for (int64_t p = threadIdx.x; p < P; p += blockDim.x) s += (float)dp[p * dy.ctot + dy.coff + oc];
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    for (int st = 128; st > 0; st >>= 1) {
-        if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) db[oc] = sh[0];
 }
 
 // ------------------------------------------------------- element-wise
@@ -418,8 +508,13 @@ int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co
     if (y32 && (!ok_view(y32) || !same_pos(x, y32) || y32->c > co)) return SG_EINVAL;
     const sg_view none = {};
     const int64_t P = (int64_t)x->n * x->d * x->h * x->w;
-    hipLaunchKernelGGL(k_conv_fwd, dim3((unsigned)((P + 63) / 64), co / 16), dim3(256), 0, (hipStream_t)hip_stream, *x,
-                       (const bf16 *)w, bias, k, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none, accumulate);
+    const unsigned gx = (unsigned)((P + 64 * FP - 1) / (64 * FP));
+    if (co % 32 == 0)
+        hipLaunchKernelGGL(k_conv_fwd<2>, dim3(gx, co / 32), dim3(256), 0, (hipStream_t)hip_stream, *x, (const bf16 *)w,
+                           bias, k, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none, accumulate);
+    else
+        hipLaunchKernelGGL(k_conv_fwd<1>, dim3(gx, co / 16), dim3(256), 0, (hipStream_t)hip_stream, *x, (const bf16 *)w,
+                           bias, k, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none, accumulate);
     return status();
 }
 
@@ -436,41 +531,56 @@ int sg_weight_prep(const float *w32, int32_t co, int32_t ci, int32_t k, void *w_
     return status();
 }
 
-static int bwd_w_chunks(const sg_view *dy, int ci, int k, int co_pad, int *chunk)
+struct BwdPlan { int nob, groups, co_pad, cblocks, K; int64_t ws_floats, bias_off; };
+
+static BwdPlan bwd_plan(const sg_view *dy, int ci, int k)
 {
+    BwdPlan b;
+    b.co_pad = (dy->c + 15) & ~15;
+    b.nob = b.co_pad % 32 == 0 ? 2 : 1;
+    b.cblocks = (ci + 15) / 16;
+    b.K = k * k * k * ci;
     const int64_t P = (int64_t)dy->n * dy->d * dy->h * dy->w;
-    const int K = k * k * k * ci;
-    const int tiles = ((K + 63) / 64) * (co_pad / 16);
-    int64_t nch = std::max<int64_t>(1, std::min<int64_t>(2048 / std::max(1, tiles), (P + 255) / 256));
-    int64_t c = (P + nch - 1) / nch;
-    c = (c + 31) / 32 * 32;
-    *chunk = (int)c;
-    return (int)((P + c - 1) / c);
+    const int64_t nchunks = (P + BPC - 1) / BPC;
+    const int64_t yz = (int64_t)(b.co_pad / (16 * b.nob)) * b.cblocks;
+    int64_t g = std::max<int64_t>(1, std::min<int64_t>(nchunks, (1024 + yz - 1) / yz));
+    // keep the partial sums within 64 Mi floats
+    g = std::max<int64_t>(1, std::min<int64_t>(g, ((int64_t)1 << 26) / ((int64_t)b.co_pad * b.K)));
+    b.groups = (int)g;
+    b.bias_off = g * b.co_pad * b.K;
+    b.ws_floats = b.bias_off + g * b.co_pad;
+    return b;
 }
 
 int64_t sg_conv3d_bwd_weight_ws(const sg_view *dy, int32_t ci, int32_t k)
 {
-    if (!ok_view(dy) || ci <= 0) return -1;
-    const int co_pad = (dy->c + 15) & ~15;
-    int chunk;
-    const int nch = bwd_w_chunks(dy, ci, k, co_pad, &chunk);
-    return (int64_t)nch * co_pad * k * k * k * ci * (int64_t)sizeof(float);
+    if (!ok_view(dy) || ci <= 0 || (k != 1 && k != 3)) return -1;
+    return bwd_plan(dy, ci, k).ws_floats * (int64_t)sizeof(float);
 }
 
 int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw, float *db,
                          float *ws, int64_t ws_bytes, void *hip_stream)
 {
-    if (!ok_view(x) || !ok_view(dy) || !same_pos(x, dy) || !dw || !ws || (k != 1 && k != 3)) return SG_EINVAL;
-    const int ci = x->c, co = dy->c, co_pad = (co + 15) & ~15, K = k * k * k * ci;
-    int chunk;
-    const int nch = bwd_w_chunks(dy, ci, k, co_pad, &chunk);
-    if (ws_bytes < (int64_t)nch * co_pad * K * (int64_t)sizeof(float)) return SG_EINVAL;
+    if (!mfma_view(x) || !ok_view(dy) || dy->ctot % 8 || dy->coff % 8 || dy->c > 256 || !same_pos(x, dy) || !dw ||
+        !ws || (k != 1 && k != 3))
+        return SG_EINVAL;
+    const int ci = x->c, co = dy->c;
+    const BwdPlan b = bwd_plan(dy, ci, k);
+    if (ws_bytes < b.ws_floats * (int64_t)sizeof(float)) return SG_EINVAL;
     hipStream_t st = (hipStream_t)hip_stream;
-    hipLaunchKernelGGL(k_conv_bwd_w, dim3((K + 63) / 64, co_pad / 16, nch), dim3(256), 0, st, *x, *dy, k, periodic_mask,
-                       chunk, co_pad, ws);
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(grid_for((int64_t)co * K)), dim3(256), 0, st, (const float *)ws, nch,
-                       co_pad, co, K, dw);
-    if (db) hipLaunchKernelGGL(k_bias_grad, dim3(co), dim3(256), 0, st, *dy, db);
+    const dim3 grid(b.groups, b.co_pad / (16 * b.nob), b.cblocks);
+    float *wsb = db ? ws + b.bias_off : nullptr;
+    if (b.nob == 2)
+        hipLaunchKernelGGL(k_conv_bwd_w<2>, grid, dim3(256), 0, st, *x, *dy, k, periodic_mask, b.groups, b.co_pad, ws,
+                           wsb);
+    else
+        hipLaunchKernelGGL(k_conv_bwd_w<1>, grid, dim3(256), 0, st, *x, *dy, k, periodic_mask, b.groups, b.co_pad, ws,
+                           wsb);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(grid_for((int64_t)co * b.K)), dim3(256), 0, st, (const float *)ws, b.groups,
+                       b.co_pad, co, b.K, dw);
+    if (db)
+        hipLaunchKernelGGL(k_reduce_chunks, dim3(grid_for(co)), dim3(256), 0, st, (const float *)wsb, b.groups, b.co_pad,
+                           co, 1, db);
     return status();
 }
 
