@@ -66,6 +66,53 @@ template <> struct Storage<LBCG_BF16S> {
 #define LBCG_NT_STORE 1
 #endif
 
+// Buffer-resource access.  A resource (base, size in bytes) is uniform over
+// the wavefront and lives in scalar registers; each lane supplies only a
+// 32-bit byte offset, so a pull costs no 64-bit address arithmetic per lane.
+// Accesses beyond the size read zero and drop writes.  Cache policy: 2 marks a
+// streamed, non-temporal access; 0 is the default.
+constexpr int CP_DEFAULT = 0, CP_STREAM = 2;
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void *base, uint64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)(uint32_t)bytes, 0x00020000);
+}
+
+template <class T, int CP>
+__device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    if constexpr (sizeof(T) == 2) {
+        const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte_off, 0, CP);
+        return __builtin_bit_cast(T, v);
+    } else if constexpr (sizeof(T) == 4) {
+        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, CP);
+        return __builtin_bit_cast(T, v);
+    } else if constexpr (sizeof(T) == 8) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, CP);
+        return __builtin_bit_cast(T, v);
+    } else {
+        static_assert(sizeof(T) == 16, "buffer element size");
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        const u4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, CP);
+        return __builtin_bit_cast(T, v);
+    }
+}
+
+template <class T, int CP>
+__device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, T val)
+{
+    if constexpr (sizeof(T) == 2) {
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, val), r, (int)byte_off, 0, CP);
+    } else if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, val), r, (int)byte_off, 0, CP);
+    } else {
+        static_assert(sizeof(T) == 8, "buffer element size");
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, val), r, (int)byte_off, 0, CP);
+    }
+}
+
 template <class T>
 __device__ inline T ld_stream(const T *p)
 {

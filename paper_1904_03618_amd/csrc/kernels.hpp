@@ -43,13 +43,34 @@ __device__ inline TileRange tile_range(int ntiles)
     return {t0 + m, nb, t1};
 }
 
+// Case constants are read-only for the whole launch: reading them through
+// the constant address space lets the compiler keep them in scalar registers
+// (scalar loads of uniform addresses) instead of per-lane vector registers.
+typedef const __attribute__((address_space(4))) DevCase DC;
+
+__device__ inline DC &case_at(const DevCase *cases, int i)
+{
+    return ((DC *)cases)[i];
+}
+
+// Tile entry (case, first node).  The tile index is the same for the whole
+// workgroup; reading it through readfirstlane tells the compiler so, which
+// keeps the case constants and every buffer base in scalar registers.
+__device__ inline int2 uniform_tile(const int2 *tiles, int t)
+{
+    typedef const __attribute__((address_space(4))) int CI;
+    const CI *p = (const CI *)tiles;
+    const int tu = __builtin_amdgcn_readfirstlane(t);
+    return make_int2(p[2 * tu], p[2 * tu + 1]);
+}
+
 struct Coord {
     int x, y, z, node;
-    int cx[3], cy[3], cz[3];     // wrapped coordinate - 1, 0, + 1 along each axis
+    int o[3][3];                 // index offset of the -1, 0, +1 neighbour along x, y, z (periodic wrap)
     bool lo[3], hi[3];           // first / last layer of the wall axis
 };
 
-__device__ inline Coord make_coord(const DevCase &C, int node)
+__device__ inline Coord make_coord(DC &C, int node)
 {
     Coord c;
     c.node = node;
@@ -58,26 +79,44 @@ __device__ inline Coord make_coord(const DevCase &C, int node)
     const int r = node - c.z * nxy;
     c.y = r / C.nx;
     c.x = r - c.y * C.nx;
-    c.cx[0] = c.x == 0 ? C.nx - 1 : c.x - 1; c.cx[1] = c.x; c.cx[2] = c.x == C.nx - 1 ? 0 : c.x + 1;
-    c.cy[0] = c.y == 0 ? C.ny - 1 : c.y - 1; c.cy[1] = c.y; c.cy[2] = c.y == C.ny - 1 ? 0 : c.y + 1;
-    c.cz[0] = c.z == 0 ? C.nz - 1 : c.z - 1; c.cz[1] = c.z; c.cz[2] = c.z == C.nz - 1 ? 0 : c.z + 1;
+    c.o[0][0] = c.x == 0 ? C.nx - 1 : -1;
+    c.o[0][1] = 0;
+    c.o[0][2] = c.x == C.nx - 1 ? 1 - C.nx : 1;
+    c.o[1][0] = c.y == 0 ? nxy - C.nx : -C.nx;
+    c.o[1][1] = 0;
+    c.o[1][2] = c.y == C.ny - 1 ? C.nx - nxy : C.nx;
+    c.o[2][0] = c.z == 0 ? C.N - nxy : -nxy;
+    c.o[2][1] = 0;
+    c.o[2][2] = c.z == C.nz - 1 ? nxy - C.N : nxy;
     c.lo[0] = C.wall == 0 && c.x == 0; c.hi[0] = C.wall == 0 && c.x == C.nx - 1;
     c.lo[1] = C.wall == 1 && c.y == 0; c.hi[1] = C.wall == 1 && c.y == C.ny - 1;
     c.lo[2] = C.wall == 2 && c.z == 0; c.hi[2] = C.wall == 2 && c.z == C.nz - 1;
     return c;
 }
 
+// Node at x + (X, Y, Z) with periodic wrap (X, Y, Z in {-1, 0, 1}).
+template <int X, int Y, int Z>
+__device__ inline int neighbour(const Coord &c)
+{
+    return c.node + c.o[0][1 + X] + c.o[1][1 + Y] + c.o[2][1 + Z];
+}
+
 // Pull source of direction i: the post-collision value at x - e_i, or, when
 // x - e_i lies beyond a wall (halfway bounce-back), the opposite direction at
 // x itself.
 template <int I>
-__device__ inline void pull_source(const DevCase &C, const Coord &c, int &src, int &dir)
+__device__ inline bool bounce(const Coord &c)
 {
     constexpr int X = ex(I), Y = ey(I), Z = ez(I);
-    const bool bb = (X == 1 && c.lo[0]) || (X == -1 && c.hi[0]) || (Y == 1 && c.lo[1]) ||
-                    (Y == -1 && c.hi[1]) || (Z == 1 && c.lo[2]) || (Z == -1 && c.hi[2]);
-    const int s = c.cx[1 - X] + C.nx * (c.cy[1 - Y] + C.ny * c.cz[1 - Z]);
-    src = bb ? c.node : s;
+    return (X == 1 && c.lo[0]) || (X == -1 && c.hi[0]) || (Y == 1 && c.lo[1]) || (Y == -1 && c.hi[1]) ||
+           (Z == 1 && c.lo[2]) || (Z == -1 && c.hi[2]);
+}
+
+template <int I>
+__device__ inline void pull_source(DC &, const Coord &c, int &src, int &dir)
+{
+    const bool bb = bounce<I>(c);
+    src = bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c);
     dir = bb ? opp(I) : I;
 }
 
@@ -89,19 +128,32 @@ struct NodeState {
     float jx, jy, jz;            // sum_i e_i f_i (the rest state carries none)
 };
 
+// Direction i and its opposite are stored next to each other ((1,2), (3,4),
+// ..., (17,18); 0 alone), so one buffer resource spans both and a bounce-back
+// lane differs from its neighbours only in the offset it supplies.
+template <int I>
+constexpr int pair_first() { return I == 0 ? 0 : ((I & 1) ? I : I - 1); }
+
 template <int ST, int I>
-__device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord &c, const float2 own,
+__device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const float2 own,
                                 NodeState &s, float &eR, float &eB)
 {
     using S = Storage<ST>;
     using T = typename S::T;
-    int src, dir;
-    pull_source<I>(C, c, src, dir);
-    const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+    constexpr int F = pair_first<I>(), W = I == 0 ? 1 : 2;
     const size_t N = (size_t)C.N;
-    const float dR = S::dec(ld_stream(&base[(size_t)dir * N + src]), a.inv_scale);
-    const float dB = S::dec(ld_stream(&base[(size_t)(Q + dir) * N + src]), a.inv_scale);
-    const float2 ps = a.rho_prev[C.node_off + src];
+    const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+    const bool bb = bounce<I>(c);
+    const uint32_t si = (uint32_t)(bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c));
+    constexpr bool hi_own = I != F, hi_opp = opp(I) != F;          // second array of the pair?
+    const bool hi = bb ? hi_opp : hi_own;
+    const uint32_t e = si + (hi ? (uint32_t)N : 0u);
+    const uint32_t off = e * (uint32_t)sizeof(T);
+    const T vr = buf_ld<T, CP_STREAM>(rsrc(base + (size_t)F * N, W * N * sizeof(T)), off);
+    const T vb = buf_ld<T, CP_STREAM>(rsrc(base + (size_t)(Q + F) * N, W * N * sizeof(T)), off);
+    const float dR = S::dec(vr, a.inv_scale);
+    const float dB = S::dec(vb, a.inv_scale);
+    const float2 ps = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, N * sizeof(float2)), si * 8u);
     const float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
     const float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
     const float h = tR + tB;
@@ -117,7 +169,7 @@ __device__ inline void pull_one(const StepArgs &a, const DevCase &C, const Coord
 }
 
 template <int ST, int I = 0>
-__device__ inline void pull_all(const StepArgs &a, const DevCase &C, const Coord &c, const float2 own,
+__device__ inline void pull_all(const StepArgs &a, DC &C, const Coord &c, const float2 own,
                                 NodeState &s, float &eR, float &eB)
 {
     if constexpr (I < Q) {
@@ -127,9 +179,10 @@ __device__ inline void pull_all(const StepArgs &a, const DevCase &C, const Coord
 }
 
 template <int ST>
-__device__ inline void pull_node(const StepArgs &a, const DevCase &C, const Coord &c, NodeState &s)
+__device__ inline void pull_node(const StepArgs &a, DC &C, const Coord &c, NodeState &s)
 {
-    const float2 own = a.rho_prev[C.node_off + c.node];
+    const float2 own = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, (size_t)C.N * sizeof(float2)),
+                                                  (uint32_t)c.node * 8u);
     float eR = 0.f, eB = 0.f;
     s.jx = s.jy = s.jz = 0.f;
     pull_all<ST>(a, C, c, own, s, eR, eB);
@@ -144,7 +197,7 @@ __device__ inline void pull_node(const StepArgs &a, const DevCase &C, const Coor
 // Force density (reading: uniform part plus buoyancy) and u = (j + F/2)/rho.
 struct Macro { float rho, inv_rho, Fx, Fy, Fz, ux, uy, uz; };
 
-__device__ inline Macro macro(const DevCase &C, const NodeState &s)
+__device__ inline Macro macro(DC &C, const NodeState &s)
 {
     Macro m;
     m.rho = s.R[0] + s.R[1];
@@ -159,7 +212,7 @@ __device__ inline Macro macro(const DevCase &C, const NodeState &s)
     return m;
 }
 
-__device__ inline float phase_field(const DevCase &C, float rR, float rB)
+__device__ inline float phase_field(DC &C, float rR, float rB)
 {
     const float a = rR * C.rin_inv[0], b = rB * C.rin_inv[1];
     return (a - b) / (a + b);
@@ -171,8 +224,8 @@ __global__ __launch_bounds__(256) void k_aux(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
     for (int t = tr.first; t < tr.end; t += tr.stride) {
-        const int2 tl = a.tiles[t];
-        const DevCase &C = a.cases[tl.x];
+        const int2 tl = uniform_tile(a.tiles, t);
+        DC &C = case_at(a.cases, tl.x);
         const int node = tl.y + (int)threadIdx.x;
         if (node >= C.N) continue;
         const Coord c = make_coord(C, node);
@@ -194,7 +247,7 @@ __global__ __launch_bounds__(256) void k_ghost(StepArgs a, const int2 *gtiles, i
 {
     for (int t = blockIdx.x; t < ngtiles; t += gridDim.x) {
         const int2 tl = gtiles[t];
-        const DevCase &C = a.cases[tl.x];
+        DC &C = case_at(a.cases, tl.x);
         const int e = tl.y + (int)threadIdx.x;
         if (e >= 2 * C.plane) continue;
         const int side = e >= C.plane ? 1 : 0;
@@ -227,25 +280,32 @@ __global__ __launch_bounds__(256) void k_ghost(StepArgs a, const int2 *gtiles, i
     }
 }
 
-// Aux value at x + e (or the ghost beyond a wall).
+// Aux value at x + e (or the ghost beyond a wall).  The aux read is issued
+// for every lane (a ghost lane reads its own node) so that no buffer access
+// sits in divergent control flow.
 template <int X, int Y, int Z>
-__device__ inline float4 aux_at(const StepArgs &a, const DevCase &C, const Coord &c)
+__device__ inline float4 aux_at(const StepArgs &a, DC &C, const Coord &c)
 {
     const bool glo = (X == -1 && c.lo[0]) || (Y == -1 && c.lo[1]) || (Z == -1 && c.lo[2]);
     const bool ghi = (X == 1 && c.hi[0]) || (Y == 1 && c.hi[1]) || (Z == 1 && c.hi[2]);
-    const int px = c.cx[1 + X], py = c.cy[1 + Y], pz = c.cz[1 + Z];
+    const uint32_t nb = (uint32_t)(glo || ghi ? c.node : neighbour<X, Y, Z>(c));
+    float4 v = buf_ld<float4, CP_DEFAULT>(rsrc(a.aux + C.node_off, (size_t)C.N * sizeof(float4)), nb * 16u);
     if (glo || ghi) {
+        // wrapped coordinates of x + e within the wall plane
+        const int px = c.x + X < 0 ? C.nx - 1 : (c.x + X >= C.nx ? 0 : c.x + X);
+        const int py = c.y + Y < 0 ? C.ny - 1 : (c.y + Y >= C.ny ? 0 : c.y + Y);
+        const int pz = c.z + Z < 0 ? C.nz - 1 : (c.z + Z >= C.nz ? 0 : c.z + Z);
         const int gi = C.wall == 0 ? py + C.ny * pz : (C.wall == 1 ? px + C.nx * pz : px + C.nx * py);
-        return a.ghost[C.ghost_off + (ghi ? C.plane : 0) + gi];
+        v = a.ghost[C.ghost_off + (ghi ? C.plane : 0) + gi];
     }
-    return a.aux[C.node_off + px + C.nx * (py + C.ny * pz)];
+    return v;
 }
 
 // Eq. (49) for rho^N (all components) and for Qbar_alpha (component alpha only).
 struct Stencil { float gx, gy, gz, Qx, Qy, Qz; };
 
 template <int I = 1>
-__device__ inline void stencil_acc(const StepArgs &a, const DevCase &C, const Coord &c, Stencil &st)
+__device__ inline void stencil_acc(const StepArgs &a, DC &C, const Coord &c, Stencil &st)
 {
     if constexpr (I < Q) {
         constexpr int X = ex(I), Y = ey(I), Z = ez(I);
@@ -260,7 +320,7 @@ __device__ inline void stencil_acc(const StepArgs &a, const DevCase &C, const Co
 
 // Eq. (52) with the quadratic joins (reading: harmonic mean at rho^N = 0,
 // zero slope where they meet tau_v^R / tau_v^B at +-delta).
-__device__ inline float tau_v(const DevCase &C, float rn)
+__device__ inline float tau_v(DC &C, float rn)
 {
     if (rn > C.delta) return C.tauR;
     if (rn < -C.delta) return C.tauB;
@@ -274,7 +334,7 @@ __device__ inline float tau_v(const DevCase &C, float rn)
 // (Eq. 10-11) and the store of both colours' deviations at the node's own
 // slots.  st: colour gradient and Q_alpha (Eq. 49); rn: the node's rho^N.
 template <int ST>
-__device__ inline void collide_node(const StepArgs &a, const DevCase &C, int node, const NodeState &s,
+__device__ inline void collide_node(const StepArgs &a, DC &C, int node, const NodeState &s,
                                     const Stencil &st, float rn)
 {
     using S = Storage<ST>;
@@ -449,10 +509,13 @@ __device__ inline void collide_node(const StepArgs &a, const DevCase &C, int nod
     for (int i = 0; i < Q; ++i) {
         const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
         const float db = fs[i] - dr;
-        st_stream(&outb[(size_t)i * N + node], S::enc(dr, a.scale));
-        st_stream(&outb[(size_t)(Q + i) * N + node], S::enc(db, a.scale));
+        const uint64_t nb = N * sizeof(T);
+        const uint32_t off = (uint32_t)node * (uint32_t)sizeof(T);
+        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)i * N, nb), off, S::enc(dr, a.scale));
+        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)(Q + i) * N, nb), off, S::enc(db, a.scale));
     }
-    a.rho_cur[C.node_off + node] = make_float2(RR, RB);
+    buf_st<float2, CP_DEFAULT>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u,
+                               make_float2(RR, RB));
 }
 
 // ------------------------------------------------------------- k_collide
@@ -461,8 +524,8 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
     for (int t = tr.first; t < tr.end; t += tr.stride) {
-        const int2 tl = a.tiles[t];
-        const DevCase &C = a.cases[tl.x];
+        const int2 tl = uniform_tile(a.tiles, t);
+        DC &C = case_at(a.cases, tl.x);
         const int node = tl.y + (int)threadIdx.x;
         if (node >= C.N) continue;
         const Coord c = make_coord(C, node);
@@ -497,7 +560,7 @@ struct FusedArgs {
 __device__ inline int ring_slot(int z) { return (z + 3) % 3; }
 
 // aux value of a node from its pulled state
-__device__ inline float4 aux_value(const DevCase &C, const NodeState &s)
+__device__ inline float4 aux_value(DC &C, const NodeState &s)
 {
     const Macro m = macro(C, s);
     const float qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
@@ -522,7 +585,7 @@ __device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int r, Stencil &
 // interior state in `keep`) and the halo, or mirror the first layer beyond a
 // wall.
 template <int ST>
-__device__ inline void fused_plane(const StepArgs &a, const DevCase &C, float4 (*ring)[FREG], int zz, int x0,
+__device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], int zz, int x0,
                                    int y0, int ax, int ay, bool active, int tx, int ty, NodeState &keep)
 {
     const int slot = ring_slot(zz);
@@ -572,7 +635,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
     const int tx = (int)threadIdx.x % FTX, ty = (int)threadIdx.x / FTX;
     for (int t = tr.first; t < tr.end; t += tr.stride) {
         const int4 tl = fa.ftiles[t];
-        const DevCase &C = a.cases[tl.x];
+        DC &C = case_at(a.cases, tl.x);
         const int x0 = tl.y, y0 = tl.z, z0 = tl.w;
         const int z1 = min(z0 + fa.zc, C.nz);
         const int ax = min(FTX, C.nx - x0), ay = min(FTY, C.ny - y0);
@@ -612,7 +675,7 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, int tile0, float *r
 {
     __shared__ double red[6][4];
     const int2 tl = a.tiles[tile0 + blockIdx.x];
-    const DevCase &C = a.cases[tl.x];
+    DC &C = case_at(a.cases, tl.x);
     const int node = tl.y + (int)threadIdx.x;
     double v[6] = {0, 0, 0, 0, 0, 0};
     if (node < C.N) {
@@ -673,7 +736,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double *partial, int n, do
 
 // ------------------------------------------------------------ utilities
 template <int I = 0>
-__device__ inline void map_all(const DevCase &C, const Coord &c, int64_t *sn, int8_t *sd)
+__device__ inline void map_all(DC &C, const Coord &c, int64_t *sn, int8_t *sd)
 {
     if constexpr (I < Q) {
         int src, dir;
@@ -686,7 +749,7 @@ __device__ inline void map_all(const DevCase &C, const Coord &c, int64_t *sn, in
 
 __global__ __launch_bounds__(256) void k_index_map(const DevCase *cases, int cid, int64_t *sn, int8_t *sd)
 {
-    const DevCase &C = cases[cid];
+    DC &C = case_at(cases, cid);
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= C.N) return;
     map_all(C, make_coord(C, node), sn, sd);
@@ -695,7 +758,7 @@ __global__ __launch_bounds__(256) void k_index_map(const DevCase *cases, int cid
 // Current-level populations f_i^k(x) (the values the next collision sees):
 // the pull of every direction, decoded to FP32.
 template <int ST, int I = 0>
-__device__ inline void get_dirs(const StepArgs &a, const DevCase &C, const Coord &c, float *out)
+__device__ inline void get_dirs(const StepArgs &a, DC &C, const Coord &c, float *out)
 {
     if constexpr (I < Q) {
         using S = Storage<ST>;
@@ -715,7 +778,7 @@ __device__ inline void get_dirs(const StepArgs &a, const DevCase &C, const Coord
 template <int ST>
 __global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out)
 {
-    const DevCase &C = a.cases[cid];
+    DC &C = case_at(a.cases, cid);
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= C.N) return;
     get_dirs<ST>(a, C, make_coord(C, node), out);
@@ -729,7 +792,7 @@ __global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out
 struct InitCase { double alpha[2]; int improved; };
 
 template <int ST, int I = 0>
-__device__ inline void init_dirs(const StepArgs &a, const DevCase &C, const Coord &c, const InitCase &ic,
+__device__ inline void init_dirs(const StepArgs &a, DC &C, const Coord &c, const InitCase &ic,
                                  const double (&r)[2], const double (&u)[3], double uu, const double *rR0,
                                  const double *rB0)
 {
@@ -764,7 +827,7 @@ __global__ __launch_bounds__(256) void k_init(StepArgs a, int cid, InitCase ic, 
                                               const double *rB0, const double *ux0, const double *uy0,
                                               const double *uz0)
 {
-    const DevCase &C = a.cases[cid];
+    DC &C = case_at(a.cases, cid);
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= C.N) return;
     const double r[2] = {rR0[node], rB0[node]};
