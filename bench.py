@@ -163,6 +163,41 @@ def cpu_baseline(p, fl, budget_s):
                       f"({dt:.1f} s)"}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def surrogate_bench(with_rt):
+    """The learned surrogate (BF16 MFMA U-Net): full-domain inference on the
+    128 x 128 x 512 Rayleigh-Taylor box and a training step on four 64^3
+    crops, against the dense BF16 matrix-core peak; optionally the gated
+    hybrid on a 32 x 32 x 128 Rayleigh-Taylor run (train, then jump 100 steps
+    at a time while the bubble and spike fronts stay within 1 lattice unit of
+    the LB run) with its time-to-solution gain over plain LB."""
+    from paper_1904_03618_amd import surrogate as S
+    inf = S.bench_unet((1, 512, 128, 128), iters=5, train=False)
+    tr = S.bench_unet((4, 64, 64, 64), iters=5, train=True)
+    res = {
+        "inference": {"shape": inf["shape"], "ms": inf["forward_ms"], "gflop": inf["forward_gflop"],
+                      "roofline": {"bound": "mfma", "achieved": inf["forward_tflops"], "peak": MFMA_BF16_PEAK_TFLOPS,
+                                   "unit": "TFLOP/s", "frac": inf["forward_tflops"] / MFMA_BF16_PEAK_TFLOPS}},
+        "training_step": {"shape": tr["shape"], "ms": tr["train_ms"], "gflop": tr["train_gflop"],
+                          "TFLOPs": tr["train_tflops"]},
+        "params": inf["params"],
+    }
+    if with_rt:
+        from paper_1904_03618_amd import surrogate_rt as R
+        rt = R.experiment(L=32, iters=1500, batch=4, gates=(1.0,))
+        g = rt["gates"]["1.0"]
+        res["rt_hybrid"] = {
+            "lattice": rt["lattice"], "jump_steps": rt["every"], "heal_steps": rt["heal"], "steps": rt["steps"],
+            "train_iters": rt["train_iters"], "train_s": rt["train_s"], "loss_first": rt["loss_first"],
+            "loss_last": rt["loss_last"], "gate_lu": 1.0, "accepted": g["accepted"], "jumps": g["jumps"],
+            "max_accepted_front_error": g["max_accepted_error"], "final_front_error": g["final_front_error"],
+            "lb_s": rt["lb_s"], "hybrid_s": g["hybrid_s"], "gain": g["gain"],
+            "persistence": g["persistence"]}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +208,9 @@ def main():
     ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused"])
     ap.add_argument("--batch-steps", type=int, default=100, help="timed steps of the impact batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--surrogate", type=int, default=1, help="time the surrogate network (1) or skip it (0)")
+    ap.add_argument("--surrogate-rt", type=int, default=1,
+                    help="run the gated surrogate/LB hybrid on a 32x32x128 Rayleigh-Taylor case (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the device copy that measures the attainable HBM rate (0: skip)")
     args = ap.parse_args()
@@ -211,6 +249,7 @@ def main():
                                                           "steps": args.steps + args.warmup}}
 
     copy = copy_probe(args.copy_probe_mib) if args.copy_probe_mib > 0 else None
+    sur = surrogate_bench(args.surrogate_rt) if args.surrogate else None
     batch = batch_bench(B, args.batch_steps, 10) if args.batch_steps > 0 else None
 
     out = {
@@ -229,6 +268,8 @@ def main():
     }
     if batch:
         out["batch"] = batch
+    if sur:
+        out["surrogate"] = sur
     if copy:
         out["copy_probe"] = copy
         out["roofline"]["frac_of_copy_probe"] = ach / copy["GBps"]

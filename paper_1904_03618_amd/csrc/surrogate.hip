@@ -372,6 +372,46 @@ __global__ void k_up2_fwd(sg_view x, sg_view y)
     }
 }
 
+// 8-channel (16-byte) forms of the two sampling layers for channel-aligned views.
+__global__ void k_up2_fwd8(sg_view x, sg_view y)
+{
+    const int g8 = y.c >> 3;
+    const int64_t n = npos(y) * g8;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / g8;
+        const int c = (int)(e - p * g8) << 3;
+        const Pos q = decode(y, p);
+        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + p * y.ctot + y.coff + c) =
+            *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const bf16 *>(x.p) +
+                                              flat(x, q.n, q.z >> 1, q.y >> 1, q.x >> 1) * x.ctot + x.coff + c);
+    }
+}
+
+__global__ void k_pool2_fwd8(sg_view x, sg_view y)
+{
+    const int g8 = y.c >> 3;
+    const int64_t n = npos(y) * g8;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = e / g8;
+        const int c = (int)(e - p * g8) << 3;
+        const Pos q = decode(y, p);
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
+                        reinterpret_cast<const bf16 *>(x.p) + flat(x, q.n, 2 * q.z + dz, 2 * q.y + dy, 2 * q.x + dx) * x.ctot +
+                        x.coff + c);
+                    #pragma unroll
+                    for (int j = 0; j < 8; ++j) s[j] += (float)v[j];
+                }
+        bf16x8 o;
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = (bf16)(0.125f * s[j]);
+        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + p * y.ctot + y.coff + c) = o;
+    }
+}
+
 __global__ void k_up2_bwd(sg_view dy, sg_view dx, int accumulate)
 {
     const int64_t n = npos(dx) * dx.c;
@@ -605,7 +645,10 @@ int sg_pool2_fwd(const sg_view *x, const sg_view *y, void *hip_stream)
 {
     if (!ok_view(x) || !ok_view(y) || !half_of(x, y)) return SG_EINVAL;
     const int64_t n = (int64_t)y->n * y->d * y->h * y->w * y->c;
-    hipLaunchKernelGGL(k_pool2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    if (mfma_view(x) && mfma_view(y))
+        hipLaunchKernelGGL(k_pool2_fwd8, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    else
+        hipLaunchKernelGGL(k_pool2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
     return status();
 }
 
@@ -621,7 +664,10 @@ int sg_up2_fwd(const sg_view *x, const sg_view *y, void *hip_stream)
 {
     if (!ok_view(x) || !ok_view(y) || !half_of(y, x)) return SG_EINVAL;
     const int64_t n = (int64_t)y->n * y->d * y->h * y->w * y->c;
-    hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    if (mfma_view(x) && mfma_view(y))
+        hipLaunchKernelGGL(k_up2_fwd8, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    else
+        hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
     return status();
 }
 

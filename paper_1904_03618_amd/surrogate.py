@@ -309,3 +309,70 @@ def lift(pred, cs2, rho_prev=None, p_in=None):
                        float(p_in if p_in is not None else 0.0), C.c_void_p(out.data_ptr()), _stream()), "lift")
     return out
 
+
+
+LEVEL = {"e1": 0, "d1": 0, "he": 0, "e2": 1, "d2": 1, "e3": 2, "d3": 2, "e4": 3}
+
+
+def flops(net):
+    """Algorithmic FLOPs (2 per multiply-add) of one forward pass and of one
+    training step (forward, weight gradients, data gradients of every layer
+    but the first) of the network at its buffer shape."""
+    n, d, h, w = net.shape
+    fwd = bwd_w = bwd_x = 0
+    for l in net.layers:
+        lv = LEVEL[l.name[:2]]
+        P = n * (d >> lv) * (h >> lv) * (w >> lv)
+        f = 2 * P * l.co * l.k ** 3 * l.ci
+        fwd += f
+        bwd_w += f
+        if l.name != "e1a":
+            bwd_x += f
+    return fwd, fwd + bwd_w + bwd_x
+
+
+def bench_unet(shape, iters=10, train=True, warmup=2):
+    """Time the forward pass (and a training step) of the network at `shape`
+    with HIP events on the current stream; returns ms and TFLOP/s."""
+    import torch
+    net = UNet(shape, seed=1, us=0.02, pmask=3)
+    n, d, h, w = shape
+    g = torch.Generator(device="cuda").manual_seed(3)
+    f = 0.1 * torch.randn((4, d * h * w), device="cuda", generator=g)
+    for b in range(n):
+        net.pack(f, (w, h, d), b=b)
+        net.pack(f, (w, h, d), b=b, target=True)
+    fl_fwd, fl_train = flops(net)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"shape": list(shape), "params": net.nparams, "forward_gflop": fl_fwd / 1e9}
+    for _ in range(warmup):
+        net.forward()
+    e0.record()
+    for _ in range(iters):
+        net.forward()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / iters
+    out.update(forward_ms=ms, forward_tflops=fl_fwd / (ms * 1e-3) / 1e12)
+    if train:
+        for _ in range(warmup):
+            net.forward(); net.mse(); net.backward(); net.adam(1e-4)
+        e0.record()
+        for _ in range(iters):
+            net.forward(); net.mse(); net.backward(); net.adam(1e-4)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / iters
+        out.update(train_gflop=fl_train / 1e9, train_ms=ms, train_tflops=fl_train / (ms * 1e-3) / 1e12)
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="Time the surrogate network's forward pass and training step")
+    ap.add_argument("--shape", default="1,512,128,128", help="batch,depth,height,width")
+    ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--no-train", action="store_true")
+    a = ap.parse_args()
+    print(json.dumps(bench_unet(tuple(int(v) for v in a.shape.split(",")), a.iters, not a.no_train)), flush=True)
