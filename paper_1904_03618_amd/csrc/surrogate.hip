@@ -160,6 +160,122 @@ __global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restr
         }
 }
 
+// 3x3x3 convolution on a brick of 16 (x) x 4 (y) x 4 (z) output positions of
+// one batch item, for tensors whose extents are multiples of the brick.  The
+// brick's input halo (18 x 6 x 6 positions) is staged in LDS one chunk of up
+// to 32 input channels at a time, so each input value is fetched from memory
+// once per chunk instead of once per tap; the 27 taps then read their B
+// fragments from LDS.  Wave w owns z-plane w of the brick: FP = 4 rows of 16
+// positions, NO blocks of 16 output channels, as in k_conv_fwd.  LDS rows are
+// padded by 16 bytes so that the 16 lanes of a fragment read (consecutive x)
+// fall into different banks.
+constexpr int BX = 16, BY = 4, BZ = 4;
+constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2, HP = HX * HY * HZ;
+constexpr int CIT = 32, LROW = CIT + 8;
+
+template <int NO>
+__global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__restrict__ W,
+                                                     const float *__restrict__ bias, int pmask, int relu, sg_view y,
+                                                     sg_view y32, int accumulate)
+{
+    __shared__ __attribute__((aligned(16))) bf16 halo[HP * LROW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, grp = lane >> 4;
+    const int nbx = x.w / BX, nby = x.h / BY, nbz = x.d / BZ;
+    int bi = blockIdx.x;
+    const int bxi = bi % nbx;
+    bi /= nbx;
+    const int byi = bi % nby;
+    bi /= nby;
+    const int bzi = bi % nbz;
+    const int n = bi / nbz;
+    const int X0 = bxi * BX, Y0 = byi * BY, Z0 = bzi * BZ;
+    const int co0 = blockIdx.y * 16 * NO;
+    const int ci = x.c, K = 27 * ci;
+    const bf16 *xp = reinterpret_cast<const bf16 *>(x.p) + x.coff;
+    const bf16 *wrow = W + (int64_t)(co0 + col) * K;
+    const bf16x8 zero = {};
+    f32x4 acc[NO][FP];
+    #pragma unroll
+    for (int o = 0; o < NO; ++o)
+        #pragma unroll
+        for (int i = 0; i < FP; ++i) acc[o][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c0 = 0; c0 < ci; c0 += CIT) {
+        const int gpt = min(CIT, ci - c0) >> 3;          // 8-channel groups per tap in this chunk
+        __syncthreads();                                  // previous chunk's fragment reads are done
+        for (int e = threadIdx.x; e < HP * gpt; e += blockDim.x) {
+            const int hp = e / gpt, c8 = e - hp * gpt;
+            const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
+            int gx = X0 - 1 + hx, gy = Y0 - 1 + hy, gz = Z0 - 1 + hz;
+            bool ok = true;
+            if (gx < 0 || gx >= x.w) {
+                if (pmask & 1) gx = gx < 0 ? gx + x.w : gx - x.w;
+                else ok = false;
+            }
+            if (gy < 0 || gy >= x.h) {
+                if (pmask & 2) gy = gy < 0 ? gy + x.h : gy - x.h;
+                else ok = false;
+            }
+            if (gz < 0 || gz >= x.d) {
+                if (pmask & 4) gz = gz < 0 ? gz + x.d : gz - x.d;
+                else ok = false;
+            }
+            bf16x8 v = zero;
+            if (ok)
+                v = *reinterpret_cast<const bf16x8 *>(
+                    xp + ((((int64_t)n * x.d + gz) * x.h + gy) * x.w + gx) * x.ctot + c0 + 8 * c8);
+            *reinterpret_cast<bf16x8 *>(&halo[hp * LROW + 8 * c8]) = v;
+        }
+        __syncthreads();
+        const int G = 27 * gpt;
+        for (int kb = 0; kb < (G + 3) >> 2; ++kb) {
+            const int g = (kb << 2) + grp;
+            bf16x8 a[NO], b[FP];
+            #pragma unroll
+            for (int o = 0; o < NO; ++o) a[o] = zero;
+            #pragma unroll
+            for (int i = 0; i < FP; ++i) b[i] = zero;
+            if (g < G) {
+                const int tap = g / gpt, c8 = g - tap * gpt;
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                #pragma unroll
+                for (int o = 0; o < NO; ++o)
+                    a[o] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * o * K + tap * ci + c0 + 8 * c8);
+                #pragma unroll
+                for (int i = 0; i < FP; ++i) {
+                    const int hp = ((wave + 1 + dz) * HY + (i + 1 + dy)) * HX + (col + 1 + dx);
+                    b[i] = *reinterpret_cast<const bf16x8 *>(&halo[hp * LROW + 8 * c8]);
+                }
+            }
+            #pragma unroll
+            for (int o = 0; o < NO; ++o)
+                #pragma unroll
+                for (int i = 0; i < FP; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
+        }
+    }
+    #pragma unroll
+    for (int o = 0; o < NO; ++o)
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int oc = co0 + 16 * o + (grp << 2) + j;
+            const bool sy = y.p && oc < y.c, s32 = y32.p && oc < y32.c;
+            if (!sy && !s32) continue;                 // padded output rows
+            const float bo = bias ? bias[oc] : 0.f;
+            #pragma unroll
+            for (int i = 0; i < FP; ++i) {
+                const int64_t pb = (((int64_t)n * x.d + Z0 + wave) * x.h + Y0 + i) * x.w + X0 + col;
+                float v = acc[o][i][j] + bo;
+                if (relu) v = fmaxf(v, 0.f);
+                if (sy) reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc] = (bf16)v;
+                if (s32) {
+                    float *out = reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc;
+                    *out = accumulate ? *out + v : v;
+                }
+            }
+        }
+}
+
 // Master weights -> BF16 [co_pad][K] and the flipped transpose
 // Wt[ci][tap' co8 + c] = W[c][tap ci + ci] with tap' the mirrored tap.
 __global__ void k_weight_prep(const float *w32, int co, int ci, int k, bf16 *wb, bf16 *wt, int co_pad, int ci_pad)
@@ -548,6 +664,18 @@ int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co
     if (y32 && (!ok_view(y32) || !same_pos(x, y32) || y32->c > co)) return SG_EINVAL;
     const sg_view none = {};
     const int64_t P = (int64_t)x->n * x->d * x->h * x->w;
+    if (k == 3 && x->w % BX == 0 && x->h % BY == 0 && x->d % BZ == 0) {
+        const unsigned nb = (unsigned)((int64_t)x->n * (x->d / BZ) * (x->h / BY) * (x->w / BX));
+        if (co % 32 == 0)
+            hipLaunchKernelGGL(k_conv3_brick<2>, dim3(nb, co / 32), dim3(256), 0, (hipStream_t)hip_stream, *x,
+                               (const bf16 *)w, bias, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none,
+                               accumulate);
+        else
+            hipLaunchKernelGGL(k_conv3_brick<1>, dim3(nb, co / 16), dim3(256), 0, (hipStream_t)hip_stream, *x,
+                               (const bf16 *)w, bias, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none,
+                               accumulate);
+        return status();
+    }
     const unsigned gx = (unsigned)((P + 64 * FP - 1) / (64 * FP));
     if (co % 32 == 0)
         hipLaunchKernelGGL(k_conv_fwd<2>, dim3(gx, co / 32), dim3(256), 0, (hipStream_t)hip_stream, *x, (const bf16 *)w,

@@ -42,6 +42,11 @@ def close(got, want, rtol=2e-5):
     (3, 7, (1, 4, 8, 8), 48, 32, 16, 32),
     (1, 0, (1, 5, 7, 9), 16, 0, 16, 4),
     (3, 5, (1, 8, 4, 8), 64, 0, 64, 128),
+    # extents that are multiples of the 16 x 4 x 4 brick (LDS-staged halo path)
+    (3, 0, (1, 4, 4, 16), 8, 0, 8, 16),
+    (3, 7, (2, 8, 4, 32), 64, 16, 48, 32),
+    (3, 3, (1, 4, 8, 16), 192, 0, 192, 64),
+    (3, 6, (1, 8, 8, 16), 16, 0, 16, 16),
 ])
 def test_conv_forward_data_and_weight_gradients(k, pmask, shape, ctot, coff, ci, co):
     import torch
