@@ -418,14 +418,26 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k
     }
 }
 
-__global__ void k_reduce_chunks(const float *ws, int nchunks, int co_pad, int co, int K, float *dw)
+// Fixed-order sum of the per-group partials in two passes: slice s of the
+// groups (g = s, s + S, ...) per thread and output, then the S slice sums.
+__global__ void k_reduce_slices(const float *ws, int groups, int co_pad, int co, int K, int S, float *tmp)
 {
     const int64_t n = (int64_t)co * K;
+    const int s = blockIdx.y;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         const int o = (int)(e / K), kc = (int)(e % K);
-        float s = 0.f;
-        for (int ch = 0; ch < nchunks; ++ch) s += ws[((int64_t)ch * co_pad + o) * K + kc];
-        dw[e] = s;
+        float acc = 0.f;
+        for (int g = s; g < groups; g += S) acc += ws[((int64_t)g * co_pad + o) * K + kc];
+        tmp[(int64_t)s * n + e] = acc;
+    }
+}
+
+__global__ void k_reduce_final(const float *tmp, int S, int64_t n, float *dw)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int s = 0; s < S; ++s) acc += tmp[(int64_t)s * n + e];
+        dw[e] = acc;
     }
 }
 
@@ -699,7 +711,7 @@ int sg_weight_prep(const float *w32, int32_t co, int32_t ci, int32_t k, void *w_
     return status();
 }
 
-struct BwdPlan { int nob, groups, co_pad, cblocks, K; int64_t ws_floats, bias_off; };
+struct BwdPlan { int nob, groups, co_pad, cblocks, K, S; int64_t ws_floats, bias_off, tmp_off, tmpb_off; };
 
 static BwdPlan bwd_plan(const sg_view *dy, int ci, int k)
 {
@@ -715,8 +727,11 @@ static BwdPlan bwd_plan(const sg_view *dy, int ci, int k)
     // keep the partial sums within 64 Mi floats
     g = std::max<int64_t>(1, std::min<int64_t>(g, ((int64_t)1 << 26) / ((int64_t)b.co_pad * b.K)));
     b.groups = (int)g;
+    b.S = (int)std::min<int64_t>(16, g);
     b.bias_off = g * b.co_pad * b.K;
-    b.ws_floats = b.bias_off + g * b.co_pad;
+    b.tmp_off = b.bias_off + g * b.co_pad;
+    b.tmpb_off = b.tmp_off + (int64_t)b.S * b.co_pad * b.K;
+    b.ws_floats = b.tmpb_off + (int64_t)b.S * b.co_pad;
     return b;
 }
 
@@ -744,11 +759,16 @@ int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t
     else
         hipLaunchKernelGGL(k_conv_bwd_w<1>, grid, dim3(256), 0, st, *x, *dy, k, periodic_mask, b.groups, b.co_pad, ws,
                            wsb);
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(grid_for((int64_t)co * b.K)), dim3(256), 0, st, (const float *)ws, b.groups,
-                       b.co_pad, co, b.K, dw);
-    if (db)
-        hipLaunchKernelGGL(k_reduce_chunks, dim3(grid_for(co)), dim3(256), 0, st, (const float *)wsb, b.groups, b.co_pad,
-                           co, 1, db);
+    const int64_t nw = (int64_t)co * b.K;
+    hipLaunchKernelGGL(k_reduce_slices, dim3(grid_for(nw), b.S), dim3(256), 0, st, (const float *)ws, b.groups, b.co_pad,
+                       co, b.K, b.S, ws + b.tmp_off);
+    hipLaunchKernelGGL(k_reduce_final, dim3(grid_for(nw)), dim3(256), 0, st, (const float *)(ws + b.tmp_off), b.S, nw, dw);
+    if (db) {
+        hipLaunchKernelGGL(k_reduce_slices, dim3(grid_for(co), b.S), dim3(256), 0, st, (const float *)wsb, b.groups,
+                           b.co_pad, co, 1, b.S, ws + b.tmpb_off);
+        hipLaunchKernelGGL(k_reduce_final, dim3(grid_for(co)), dim3(256), 0, st, (const float *)(ws + b.tmpb_off), b.S,
+                           (int64_t)co, db);
+    }
     return status();
 }
 
