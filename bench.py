@@ -186,11 +186,13 @@ def surrogate_bench(with_rt):
     }
     if with_rt:
         from paper_1904_03618_amd import surrogate_rt as R
-        rt = R.experiment(L=32, iters=1500, batch=4, gates=(1.0,))
+        rt = R.experiment(L=32, gates=(1.0,))
         g = rt["gates"]["1.0"]
         res["rt_hybrid"] = {
             "lattice": rt["lattice"], "jump_steps": rt["every"], "heal_steps": rt["heal"], "steps": rt["steps"],
-            "train_iters": rt["train_iters"], "train_s": rt["train_s"], "loss_first": rt["loss_first"],
+            "train_amps": rt["train_amps"], "val_amp": rt["val_amp"], "eval_amp": rt["eval_amp"],
+            "train_iters": rt["train_iters"], "selected_after": rt["selected_after"], "validation": rt["validation"],
+            "train_s": rt["train_s"], "loss_first": rt["loss_first"],
             "loss_last": rt["loss_last"], "gate_lu": 1.0, "accepted": g["accepted"], "jumps": g["jumps"],
             "max_accepted_front_error": g["max_accepted_error"], "final_front_error": g["final_front_error"],
             "lb_s": rt["lb_s"], "hybrid_s": g["hybrid_s"], "gain": g["gain"],

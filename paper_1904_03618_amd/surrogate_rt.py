@@ -89,17 +89,20 @@ def fronts(rhoN, box):
     return tuple(res)
 
 
-def train(net, trajs, box, lag, iters=400, lr=1e-3, lr_min=1e-5, seed=0, log=None):
+def train(net, trajs, box, lag, iters=400, lr=1e-3, lr_min=1e-5, seed=0, it0=0, total=None, log=None):
     """Adam on (fields_t -> fields_{t+lag snapshots}) pairs drawn at random
     from the trajectories, one pair per batch item, with a cosine learning
-    rate from lr to lr_min; a network shorter than the box in z trains on
-    z-slabs that stay inside the box.  Returns the loss history."""
+    rate from lr to lr_min over `total` iterations (this call runs iterations
+    it0 .. it0 + iters - 1 of that schedule); a network shorter than the box in
+    z trains on z-slabs that stay inside the box.  Returns the loss history."""
     nz = box[2]
     slab = net.shape[1]
     assert slab <= nz
-    rng = np.random.default_rng(seed)
+    total = iters if total is None else total
+    rng = np.random.default_rng(seed + it0)
     hist = []
-    for it in range(iters):
+    for k in range(iters):
+        it = it0 + k
         for b in range(net.shape[0]):
             tr = trajs[int(rng.integers(len(trajs)))]
             i = int(rng.integers(len(tr) - lag))
@@ -109,12 +112,20 @@ def train(net, trajs, box, lag, iters=400, lr=1e-3, lr_min=1e-5, seed=0, log=Non
         net.forward()
         net.mse()
         net.backward()
-        net.adam(lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * it / max(1, iters - 1))))
-        if it % 50 == 0 or it == iters - 1:
+        net.adam(lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * it / max(1, total - 1))))
+        if it % 50 == 0 or k == iters - 1:
             hist.append((it, net.loss[0].item()))
             if log:
                 log(f"train it {it} loss {hist[-1][1]:.3e}")
     return hist
+
+
+def score(h):
+    """Model-selection key of a hybrid run: a run that ends within 1 l.u. of
+    the LB fronts beats one that does not; then more accepted jumps; then a
+    smaller final error."""
+    ok = bool(np.isfinite(h["final_front_error"]) and h["final_front_error"] <= 1.0)
+    return (ok, h["accepted"], -float(h["final_front_error"]) if np.isfinite(h["final_front_error"]) else -1e9)
 
 
 def full_domain_net(trained, box):
@@ -219,12 +230,16 @@ def hybrid(net, p, fl, ref_fronts, every, t_start, t_end, heal=20, gate=1.0, use
                 accepted=sum(r["accepted"] for r in rec), jumps=len(rec))
 
 
-def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, iters=2000,
-               heal=20, rec=20, batch=2, t_start=None, lr=5e-4, lr_min=1e-5, gates=(1.0, 0.5), log=None):
+def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, val_amp=0.045,
+               iters=3000, segments=6, heal=20, rec=20, batch=4, t_start=None, lr=1e-3, lr_min=1e-5,
+               gates=(1.0, 0.5), log=None):
     """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
-    steps apart from snapshots every `rec` steps); on the held-out amplitude,
-    run the gated hybrid at each gate, the same gate with persistence in
-    place of the network, and the plain LB run.  Returns a summary."""
+    steps apart from snapshots every `rec` steps) in `segments` pieces of one
+    cosine schedule; after each piece the gated hybrid runs on a validation
+    amplitude (val_amp, neither trained on nor evaluated) and the best weights
+    by `score` are kept.  On the held-out amplitude eval_amp, run the gated
+    hybrid at each gate, the same gate with persistence in place of the
+    network, and the plain LB run.  Returns a summary."""
     import math
     import torch
     steps = steps if steps is not None else int(4.5 * math.sqrt(L / 2e-5)) // every * every
@@ -239,23 +254,40 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
         gen += w
         if log:
             log(f"trajectory amp {a}: {len(tr)} snapshots, {w:.2f} s")
+    stride = math.gcd(every, heal) if heal else every
+    pv, flv = case(L, val_amp)
+    ref_val = reference(pv, flv, steps, stride)
     p, fl = case(L, eval_amp)
     box = (p["nx"], p["ny"], p["nz"])
-    stride = math.gcd(every, heal) if heal else every
     ref = reference(p, fl, steps, stride)
     net = S.UNet((batch, p["nz"], p["ny"], p["nx"]), seed=7, us=0.02, pmask=3)
+    full = S.UNet((1, p["nz"], p["ny"], p["nx"]), seed=0, us=0.02, pmask=3)
     torch.cuda.synchronize()
     t0 = time.time()
-    hist = train(net, trajs, box, every // rec, iters=iters, lr=lr, lr_min=lr_min, log=log)
+    hist, best, val = [], None, []
+    per_seg = max(1, iters // max(1, segments))
+    for seg in range(max(1, segments)):
+        n_it = per_seg if seg < segments - 1 else iters - per_seg * (segments - 1)
+        hist += train(net, trajs, box, every // rec, iters=n_it, lr=lr, lr_min=lr_min, it0=seg * per_seg, total=iters,
+                      log=log)
+        full.load_state(net.state_dict())
+        hv = hybrid(full, pv, flv, ref_val, every, t_start, steps, heal=heal, gate=1.0)
+        key = score(hv)
+        val.append(dict(iters=seg * per_seg + n_it, accepted=hv["accepted"], final_front_error=hv["final_front_error"]))
+        if log:
+            log(f"validation after {val[-1]['iters']} iterations: accepted {hv['accepted']}/{hv['jumps']}, "
+                f"final front error {hv['final_front_error']:.3f}")
+        if best is None or key > best[0]:
+            best = (key, net.state_dict(), seg)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     del trajs
-    full = full_domain_net(net, box)
+    full.load_state(best[1])
     lb = lb_time(p, fl, t_start, steps)
     res = dict(lattice=[p["nx"], p["ny"], p["nz"]], every=every, steps=steps, t_start=t_start, heal=heal,
-               train_amps=list(train_amps), eval_amp=eval_amp, params=net.nparams, train_iters=iters, batch=batch,
-               train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]), lb_s=lb,
-               trajectory_s=gen, gates={})
+               train_amps=list(train_amps), val_amp=val_amp, eval_amp=eval_amp, params=net.nparams, train_iters=iters,
+               batch=batch, train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]),
+               validation=val, selected_after=val[best[2]]["iters"], lb_s=lb, trajectory_s=gen, gates={})
     for g in gates:
         hyb = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g)
         per = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g, use_net=False)
@@ -279,9 +311,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="Train the surrogate on Rayleigh-Taylor LB runs and measure the "
                                              "gated hybrid against plain LB")
     ap.add_argument("--L", type=int, default=64)
-    ap.add_argument("--iters", type=int, default=4000)
-    ap.add_argument("--batch", type=int, default=2)
-    ap.add_argument("--lr", type=float, default=5e-4)
+    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--heal", type=int, default=20)
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
