@@ -66,15 +66,15 @@ def dominant(kt, storage):
     return "k_collide", kt["collide"][0] / kt["collide"][1], COLLIDE_BYTES[storage]
 
 
-def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto"):
+def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto", kernel_steps=200):
+    """Time `steps` steps (no per-kernel events inside the timed region), then,
+    if timing, `kernel_steps` more steps with HIP event pairs around every
+    kernel for the per-kernel averages.  Fields are taken after the timed
+    steps."""
     import torch
     s = B.Solver(cases, storage=storage, kernel=kernel)
     try:
         s.step(warmup)
-        torch.cuda.synchronize()
-        if timing:
-            B.lbcg_timing(s.h, 1)
-            B.lbcg_timing_read(s.h)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -83,9 +83,14 @@ def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto"):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        kt = B.lbcg_timing_read(s.h) if timing else None
-        fl = s.fields(0)
-        return ms, kt, {k: v.double() for k, v in fl.items() if k != "diag"}
+        fl = {k: v.double() for k, v in s.fields(0).items() if k != "diag"}
+        kt = None
+        if timing:
+            B.lbcg_timing(s.h, 1)
+            B.lbcg_timing_read(s.h)
+            s.step(kernel_steps)
+            kt = B.lbcg_timing_read(s.h)
+        return ms, kt, fl
     finally:
         s.close()
 
