@@ -204,6 +204,22 @@ int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches);
 int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id);
 int32_t lbcg_storage_bytes(const lbcg_handle *h);
 
+/* Checkpoint / resume.  The state of a handle at its current level is the
+ * stored population values of every case (raw bits, storage format of the
+ * handle), the colour densities their writers stored with them, and the
+ * step count; everything else (aux and ghost layers) is recomputed by the
+ * next step.  lbcg_checkpoint_bytes gives the size of that image (-1 for a
+ * bad handle).  lbcg_checkpoint_save synchronises the handle's stream and
+ * copies the image into caller-owned HOST memory of at least that size.
+ * lbcg_checkpoint_load restores an image into a handle created with the same
+ * case shapes and storage format (parameters other than the shapes are the
+ * handle's own); the next steps then continue bit for bit as the saved handle
+ * would have.  Errors: LBCG_ESTATE, LBCG_EINVAL (NULL buffer, too small, or an
+ * image of another shape/format), LBCG_EDEVICE. */
+int64_t lbcg_checkpoint_bytes(const lbcg_handle *h);
+int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes);
+int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes);
+
 #ifdef __cplusplus
 }
 #endif

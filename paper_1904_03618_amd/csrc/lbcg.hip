@@ -376,6 +376,21 @@ int check_handle(const lbcg_handle *h)
 
 }  // namespace
 
+// Checkpoint image: header, then the current level's populations of every
+// case (pop[cur]) and the writers' densities of that level (rho2[(t+1)&1]).
+namespace {
+struct CkptHeader {
+    char magic[8];
+    int64_t version, storage, ncases, total_pop, total_nodes, steps;
+};
+constexpr char kMagic[8] = {'L', 'B', 'C', 'G', 'C', 'K', 'P', 'T'};
+
+int64_t ckpt_bytes(const lbcg_handle *h)
+{
+    return (int64_t)sizeof(CkptHeader) + (int64_t)h->elem * h->total_pop + (int64_t)sizeof(float2) * h->total_nodes;
+}
+}  // namespace
+
 extern "C" {
 
 const char *lbcg_last_error(void) { return g_err.c_str(); }
@@ -658,6 +673,57 @@ int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f)
     default: hipLaunchKernelGGL(k_get_pop<LBCG_BF16S>, g, b, 0, h->stream, a, case_id, f); break;
     }
     HIPCHK(hipGetLastError());
+    return LBCG_OK;
+}
+
+int64_t lbcg_checkpoint_bytes(const lbcg_handle *h)
+{
+    if (!h || !h->alive) return -1;
+    return ckpt_bytes(h);
+}
+
+int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!host || bytes < ckpt_bytes(h)) return fail(LBCG_EINVAL, "checkpoint buffer NULL or too small");
+    CkptHeader hd;
+    std::memcpy(hd.magic, kMagic, 8);
+    hd.version = 1;
+    hd.storage = h->storage;
+    hd.ncases = h->ncases;
+    hd.total_pop = h->total_pop;
+    hd.total_nodes = h->total_nodes;
+    hd.steps = h->steps;
+    char *p = static_cast<char *>(host);
+    std::memcpy(p, &hd, sizeof hd);
+    p += sizeof hd;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    HIPCHK(hipMemcpy(p, h->pop[h->cur], (size_t)h->elem * h->total_pop, hipMemcpyDeviceToHost));
+    p += (size_t)h->elem * h->total_pop;
+    HIPCHK(hipMemcpy(p, h->rho2[(h->steps + 1) & 1], sizeof(float2) * h->total_nodes, hipMemcpyDeviceToHost));
+    return LBCG_OK;
+}
+
+int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes)
+{
+    int rc = check_handle(h);
+    if (rc) return rc;
+    if (!host || bytes < (int64_t)sizeof(CkptHeader)) return fail(LBCG_EINVAL, "checkpoint buffer NULL or too small");
+    CkptHeader hd;
+    std::memcpy(&hd, host, sizeof hd);
+    if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1) return fail(LBCG_EINVAL, "not a checkpoint image");
+    if (hd.storage != h->storage || hd.ncases != h->ncases || hd.total_pop != h->total_pop ||
+        hd.total_nodes != h->total_nodes || hd.steps < 0)
+        return fail(LBCG_EINVAL, "checkpoint of another case shape or storage format");
+    if (bytes < ckpt_bytes(h)) return fail(LBCG_EINVAL, "checkpoint buffer too small");
+    const char *p = static_cast<const char *>(host) + sizeof hd;
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->steps = hd.steps;
+    h->cur = (int)(hd.steps & 1);       // the handle keeps pop[steps & 1] as the current level
+    HIPCHK(hipMemcpy(h->pop[h->cur], p, (size_t)h->elem * h->total_pop, hipMemcpyHostToDevice));
+    p += (size_t)h->elem * h->total_pop;
+    HIPCHK(hipMemcpy(h->rho2[(h->steps + 1) & 1], p, sizeof(float2) * h->total_nodes, hipMemcpyHostToDevice));
     return LBCG_OK;
 }
 

@@ -23,7 +23,8 @@ STORAGE = {"fp32": LBCG_FP32, "fp16s": LBCG_FP16S, "bf16s": LBCG_BF16S}
 # Every symbol include/lbcg.h declares.
 EXPORTS = ("lbcg_init", "lbcg_step", "lbcg_moments", "lbcg_free", "lbcg_last_error",
            "lbcg_steps_done", "lbcg_index_map", "lbcg_get_populations", "lbcg_case_nodes",
-           "lbcg_storage_bytes", "lbcg_timing", "lbcg_timing_read", "lbcg_set_fields")
+           "lbcg_storage_bytes", "lbcg_timing", "lbcg_timing_read", "lbcg_set_fields", "lbcg_checkpoint_bytes",
+           "lbcg_checkpoint_save", "lbcg_checkpoint_load")
 
 
 class LbcgError(RuntimeError):
@@ -98,6 +99,12 @@ def load():
     L.lbcg_timing_read.restype = C.c_int
     L.lbcg_set_fields.argtypes = [vp, i32, C.POINTER(lbcg_fields)]
     L.lbcg_set_fields.restype = C.c_int
+    L.lbcg_checkpoint_bytes.argtypes = [vp]
+    L.lbcg_checkpoint_bytes.restype = i64
+    L.lbcg_checkpoint_save.argtypes = [vp, vp, i64]
+    L.lbcg_checkpoint_save.restype = C.c_int
+    L.lbcg_checkpoint_load.argtypes = [vp, vp, i64]
+    L.lbcg_checkpoint_load.restype = C.c_int
     _lib = L
     return L
 
@@ -231,6 +238,21 @@ def lbcg_get_populations(h, case_id):
     f = torch.empty(2 * 19 * N, dtype=torch.float32, device="cuda")
     _check(load().lbcg_get_populations(C.c_void_p(h), int(case_id), C.c_void_p(f.data_ptr())))
     return f.view(2, 19, N)
+
+
+def lbcg_checkpoint_save(h):
+    """The handle's state image as a bytes object (host memory)."""
+    n = int(load().lbcg_checkpoint_bytes(C.c_void_p(h)))
+    if n < 0:
+        raise LbcgError(LBCG_ESTATE, "invalid handle")
+    buf = C.create_string_buffer(n)
+    _check(load().lbcg_checkpoint_save(C.c_void_p(h), buf, n))
+    return buf.raw
+
+
+def lbcg_checkpoint_load(h, image: bytes):
+    buf = C.create_string_buffer(image, len(image))
+    return _check(load().lbcg_checkpoint_load(C.c_void_p(h), buf, len(image)))
 
 
 class Solver:

@@ -96,3 +96,7 @@ def test_calls_on_null_handle_fail_cleanly():
     assert L.lbcg_moments(None, 0, None, None, None, None, None, None, None) == B.LBCG_ESTATE
     assert L.lbcg_steps_done(None) == -1
     assert L.lbcg_case_nodes(None, 0) == -1
+    assert L.lbcg_checkpoint_bytes(None) == -1
+    buf = C.create_string_buffer(64)
+    assert L.lbcg_checkpoint_save(None, buf, 64) == B.LBCG_ESTATE
+    assert L.lbcg_checkpoint_load(None, buf, 64) == B.LBCG_ESTATE
