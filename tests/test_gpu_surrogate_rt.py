@@ -26,3 +26,28 @@ def test_surrogate_gated_hybrid_on_rayleigh_taylor():
     assert g["jumps"] > 0
     assert g["max_accepted_error"] <= 1.0
     assert g["accepted"] > g["persistence"]["accepted"]
+
+
+def test_rejected_jumps_leave_the_lb_run_untouched():
+    """The gate as the second fallback: a network with a large random head
+    predicts fronts far from the LB run, every jump is rejected, and the
+    hybrid then takes exactly the plain LB steps, so its final fronts equal
+    the reference run's bit for bit (front error exactly 0)."""
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1904_03618_amd import surrogate as S
+    from paper_1904_03618_amd import surrogate_rt as R
+    p, fl = R.case(16, 0.05)
+    every, heal, steps = 100, 20, 1200
+    ref = R.reference(p, fl, steps, 20)
+    net = S.UNet((1, p["nz"], p["ny"], p["nx"]), seed=3, us=0.02, pmask=3)
+    head = net.L["head"]
+    rng = np.random.default_rng(5)
+    head.w.copy_(torch.tensor(rng.standard_normal(tuple(head.w.shape)).astype(np.float32) * 5.0))
+    head.prep()
+    h = R.hybrid(net, p, fl, ref, every, 200, steps, heal=heal, gate=1.0)
+    print(h["accepted"], h["jumps"], h["final_front_error"], flush=True)
+    assert h["jumps"] > 0 and h["accepted"] == 0
+    assert h["final_front_error"] == 0.0
