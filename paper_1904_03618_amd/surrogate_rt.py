@@ -231,7 +231,7 @@ def hybrid(net, p, fl, ref_fronts, every, t_start, t_end, heal=20, gate=1.0, use
 
 
 def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, val_amp=0.045,
-               iters=3000, segments=6, heal=20, rec=20, batch=4, t_start=None, lr=1e-3, lr_min=1e-5,
+               iters=3000, segments=6, heal=20, rec=20, batch=4, slab=None, t_start=None, lr=1e-3, lr_min=1e-5,
                gates=(1.0, 0.5), log=None):
     """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
     steps apart from snapshots every `rec` steps) in `segments` pieces of one
@@ -260,7 +260,7 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     p, fl = case(L, eval_amp)
     box = (p["nx"], p["ny"], p["nz"])
     ref = reference(p, fl, steps, stride)
-    net = S.UNet((batch, p["nz"], p["ny"], p["nx"]), seed=7, us=0.02, pmask=3)
+    net = S.UNet((batch, slab or p["nz"], p["ny"], p["nx"]), seed=7, us=0.02, pmask=3)
     full = S.UNet((1, p["nz"], p["ny"], p["nx"]), seed=0, us=0.02, pmask=3)
     torch.cuda.synchronize()
     t0 = time.time()
@@ -286,7 +286,7 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     lb = lb_time(p, fl, t_start, steps)
     res = dict(lattice=[p["nx"], p["ny"], p["nz"]], every=every, steps=steps, t_start=t_start, heal=heal,
                train_amps=list(train_amps), val_amp=val_amp, eval_amp=eval_amp, params=net.nparams, train_iters=iters,
-               batch=batch, train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]),
+               batch=batch, train_shape=list(net.shape), snapshot_every=rec, train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]),
                validation=val, selected_after=val[best[2]]["iters"], lb_s=lb, trajectory_s=gen, gates={})
     for g in gates:
         hyb = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g)
@@ -315,9 +315,13 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--heal", type=int, default=20)
+    ap.add_argument("--rec", type=int, default=20, help="snapshot interval of the training trajectories")
+    ap.add_argument("--slab", type=int, default=0, help="train on z-slabs of this depth (0: whole box)")
+    ap.add_argument("--segments", type=int, default=6)
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
-    res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, log=lambda m: print(m, flush=True))
+    res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, rec=a.rec, slab=a.slab or None,
+                     segments=a.segments, log=lambda m: print(m, flush=True))
     txt = json.dumps(res)
     print(txt, flush=True)
     if a.out:
