@@ -139,3 +139,22 @@ def test_galilean_invariance_improved_not_original():
         print("improved", improved, "centroid shift", shift, "shape difference", shape)
     assert abs(out[1][0] - u0 * T) < 0.5 and out[1][1] < 0.2
     assert abs(out[0][0] - u0 * T) > 1.5 and out[0][1] > 0.5
+
+
+def test_shear_wave_decay_gives_the_viscosity():
+    """Single phase (alpha = 1/3, one colour): a sinusoidal shear wave
+    u_x = U sin(k z) decays as exp(-nu k^2 t) with nu = c_s^2 (tau_v - 1/2),
+    c_s^2 = 1/3 (the viscosity relation stated with Eq. 52)."""
+    nz, U, T = 32, 1e-3, 400
+    for tau in (0.8, 1.3):
+        p = dict(W.DEFAULTS)
+        p.update(nx=1, ny=1, nz=nz, rho_in=(1.0, 1.0), alpha=(1 / 3, 1 / 3), tau_v=(tau, tau), A=(0.0, 0.0))
+        k = 2 * np.pi / nz
+        ux = U * np.sin(k * np.arange(nz))
+        f = O.init(p, np.ones(nz), np.zeros(nz), ux, np.zeros(nz), np.zeros(nz))
+        O.run(p, f, T)
+        u = O.fields(p, f)["ux"]
+        amp = 2.0 / nz * np.sum(u * np.sin(k * np.arange(nz)))
+        nu = np.log(U / amp) / (k * k * T)
+        print("tau", tau, "nu measured", nu, "expected", (tau - 0.5) / 3)
+        assert abs(nu / ((tau - 0.5) / 3.0) - 1.0) < 0.01
