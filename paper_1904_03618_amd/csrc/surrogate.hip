@@ -160,24 +160,25 @@ __global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restr
         }
 }
 
-// 3x3x3 convolution on a brick of 16 (x) x 4 (y) x 4 (z) output positions of
+// 3x3x3 convolution on a brick of 16 (x) x 4 (y) x 4 ZW (z) output positions of
 // one batch item, for tensors whose extents are multiples of the brick.  The
-// brick's input halo (18 x 6 x 6 positions) is staged in LDS one chunk of up
-// to 32 input channels at a time, so each input value is fetched from memory
+// brick's input halo (18 x 6 x (4 ZW + 2) positions) is staged in LDS one chunk
+// of CT input channels at a time, so each input value is fetched from memory
 // once per chunk instead of once per tap; the 27 taps then read their B
-// fragments from LDS.  Wave w owns z-plane w of the brick: FP = 4 rows of 16
-// positions, NO blocks of 16 output channels, as in k_conv_fwd.  LDS rows are
-// padded by 16 bytes so that the 16 lanes of a fragment read (consecutive x)
-// fall into different banks.
-constexpr int BX = 16, BY = 4, BZ = 4;
-constexpr int HX = BX + 2, HY = BY + 2, HZ = BZ + 2, HP = HX * HY * HZ;
-constexpr int CIT = 32, LROW = CIT + 8;
+// fragments from LDS.  Wave w owns z-planes w ZW .. w ZW + ZW - 1 of the brick
+// (4 ZW rows of 16 positions) and NO blocks of 16 output channels.  Layers with
+// few input channels use ZW = 2, CT = 16: twice the MFMA work per staged halo at
+// the same LDS size.  LDS rows are padded by 16 bytes so that the 16 lanes of a
+// fragment read (consecutive x) fall into different banks.
+constexpr int BX = 16, BY = 4;
+constexpr int HX = BX + 2, HY = BY + 2;
 
-template <int NO>
+template <int NO, int ZW, int CT>
 __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__restrict__ W,
                                                      const float *__restrict__ bias, int pmask, int relu, sg_view y,
                                                      sg_view y32, int accumulate)
 {
+    constexpr int BZ = 4 * ZW, HZ = BZ + 2, HP = HX * HY * HZ, LROW = CT + 8, NF = 4 * ZW;
     __shared__ __attribute__((aligned(16))) bf16 halo[HP * LROW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
@@ -195,14 +196,14 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
     const bf16 *xp = reinterpret_cast<const bf16 *>(x.p) + x.coff;
     const bf16 *wrow = W + (int64_t)(co0 + col) * K;
     const bf16x8 zero = {};
-    f32x4 acc[NO][FP];
+    f32x4 acc[NO][NF];
     #pragma unroll
     for (int o = 0; o < NO; ++o)
         #pragma unroll
-        for (int i = 0; i < FP; ++i) acc[o][i] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < NF; ++i) acc[o][i] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int c0 = 0; c0 < ci; c0 += CIT) {
-        const int gpt = min(CIT, ci - c0) >> 3;          // 8-channel groups per tap in this chunk
+    for (int c0 = 0; c0 < ci; c0 += CT) {
+        const int gpt = min(CT, ci - c0) >> 3;           // 8-channel groups per tap in this chunk
         __syncthreads();                                  // previous chunk's fragment reads are done
         for (int e = threadIdx.x; e < HP * gpt; e += blockDim.x) {
             const int hp = e / gpt, c8 = e - hp * gpt;
@@ -231,11 +232,11 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
         const int G = 27 * gpt;
         for (int kb = 0; kb < (G + 3) >> 2; ++kb) {
             const int g = (kb << 2) + grp;
-            bf16x8 a[NO], b[FP];
+            bf16x8 a[NO], b[NF];
             #pragma unroll
             for (int o = 0; o < NO; ++o) a[o] = zero;
             #pragma unroll
-            for (int i = 0; i < FP; ++i) b[i] = zero;
+            for (int i = 0; i < NF; ++i) b[i] = zero;
             if (g < G) {
                 const int tap = g / gpt, c8 = g - tap * gpt;
                 const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
@@ -243,15 +244,16 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
                 for (int o = 0; o < NO; ++o)
                     a[o] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * o * K + tap * ci + c0 + 8 * c8);
                 #pragma unroll
-                for (int i = 0; i < FP; ++i) {
-                    const int hp = ((wave + 1 + dz) * HY + (i + 1 + dy)) * HX + (col + 1 + dx);
+                for (int i = 0; i < NF; ++i) {
+                    const int zl = wave * ZW + i / 4, yl = i % 4;
+                    const int hp = ((zl + 1 + dz) * HY + (yl + 1 + dy)) * HX + (col + 1 + dx);
                     b[i] = *reinterpret_cast<const bf16x8 *>(&halo[hp * LROW + 8 * c8]);
                 }
             }
             #pragma unroll
             for (int o = 0; o < NO; ++o)
                 #pragma unroll
-                for (int i = 0; i < FP; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
+                for (int i = 0; i < NF; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
         }
     }
     #pragma unroll
@@ -263,8 +265,9 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
             if (!sy && !s32) continue;                 // padded output rows
             const float bo = bias ? bias[oc] : 0.f;
             #pragma unroll
-            for (int i = 0; i < FP; ++i) {
-                const int64_t pb = (((int64_t)n * x.d + Z0 + wave) * x.h + Y0 + i) * x.w + X0 + col;
+            for (int i = 0; i < NF; ++i) {
+                const int zl = wave * ZW + i / 4, yl = i % 4;
+                const int64_t pb = (((int64_t)n * x.d + Z0 + zl) * x.h + Y0 + yl) * x.w + X0 + col;
                 float v = acc[o][i][j] + bo;
                 if (relu) v = fmaxf(v, 0.f);
                 if (sy) reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc] = (bf16)v;
@@ -274,6 +277,15 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
                 }
             }
         }
+}
+
+template <int NO, int ZW, int CT>
+static void launch_brick(const sg_view *x, const void *w, const float *bias, int co, int pmask, int relu,
+                         const sg_view &y, const sg_view &y32, int accumulate, hipStream_t st)
+{
+    const unsigned nb = (unsigned)((int64_t)x->n * (x->d / (4 * ZW)) * (x->h / BY) * (x->w / BX));
+    hipLaunchKernelGGL((k_conv3_brick<NO, ZW, CT>), dim3(nb, co / (16 * NO)), dim3(256), 0, st, *x, (const bf16 *)w,
+                       bias, pmask, relu, y, y32, accumulate);
 }
 
 // Master weights -> BF16 [co_pad][K] and the flipped transpose
@@ -676,16 +688,17 @@ int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co
     if (y32 && (!ok_view(y32) || !same_pos(x, y32) || y32->c > co)) return SG_EINVAL;
     const sg_view none = {};
     const int64_t P = (int64_t)x->n * x->d * x->h * x->w;
-    if (k == 3 && x->w % BX == 0 && x->h % BY == 0 && x->d % BZ == 0) {
-        const unsigned nb = (unsigned)((int64_t)x->n * (x->d / BZ) * (x->h / BY) * (x->w / BX));
-        if (co % 32 == 0)
-            hipLaunchKernelGGL(k_conv3_brick<2>, dim3(nb, co / 32), dim3(256), 0, (hipStream_t)hip_stream, *x,
-                               (const bf16 *)w, bias, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none,
-                               accumulate);
-        else
-            hipLaunchKernelGGL(k_conv3_brick<1>, dim3(nb, co / 16), dim3(256), 0, (hipStream_t)hip_stream, *x,
-                               (const bf16 *)w, bias, periodic_mask, relu, y ? *y : none, y32 ? *y32 : none,
-                               accumulate);
+    if (k == 3 && x->w % BX == 0 && x->h % BY == 0 && x->d % 4 == 0) {
+        hipStream_t st = (hipStream_t)hip_stream;
+        const sg_view yv = y ? *y : none, y32v = y32 ? *y32 : none;
+        const bool deep = x->c % 32 != 0 && x->d % 8 == 0;   // few or odd channel counts: two planes per wave
+        if (co % 32 == 0) {
+            if (deep) launch_brick<2, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+            else launch_brick<2, 1, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+        } else {
+            if (deep) launch_brick<1, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+            else launch_brick<1, 1, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+        }
         return status();
     }
     const unsigned gx = (unsigned)((P + 64 * FP - 1) / (64 * FP));
