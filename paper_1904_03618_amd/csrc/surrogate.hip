@@ -288,6 +288,42 @@ static void launch_brick(const sg_view *x, const void *w, const float *bias, int
                        bias, pmask, relu, y, y32, accumulate);
 }
 
+// 1x1x1 convolution with few outputs (the network head): one position per
+// lane, the weight rows read as wave-uniform vectors, FP32 dot products.  The
+// layer moves ~3x more bytes than it computes, so it is written for HBM.
+template <int NOUT>
+__global__ __launch_bounds__(256) void k_conv1_small(sg_view x, const bf16 *__restrict__ W,
+                                                     const float *__restrict__ bias, int relu, sg_view y, sg_view y32,
+                                                     int accumulate)
+{
+    const int64_t P = npos(x);
+    const int ci = x.c, g8 = ci >> 3;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        float acc[NOUT];
+        #pragma unroll
+        for (int o = 0; o < NOUT; ++o) acc[o] = bias ? bias[o] : 0.f;
+        const bf16 *xr = reinterpret_cast<const bf16 *>(x.p) + p * x.ctot + x.coff;
+        for (int g = 0; g < g8; ++g) {
+            const bf16x8 v = *reinterpret_cast<const bf16x8 *>(xr + 8 * g);
+            #pragma unroll
+            for (int o = 0; o < NOUT; ++o) {
+                const bf16x8 w = *reinterpret_cast<const bf16x8 *>(W + (int64_t)o * ci + 8 * g);
+                #pragma unroll
+                for (int j = 0; j < 8; ++j) acc[o] = __builtin_fmaf((float)w[j], (float)v[j], acc[o]);
+            }
+        }
+        #pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+            float v = relu ? fmaxf(acc[o], 0.f) : acc[o];
+            if (y.p && o < y.c) reinterpret_cast<bf16 *>(y.p)[p * y.ctot + y.coff + o] = (bf16)v;
+            if (y32.p && o < y32.c) {
+                float *out = reinterpret_cast<float *>(y32.p) + p * y32.ctot + y32.coff + o;
+                *out = accumulate ? *out + v : v;
+            }
+        }
+    }
+}
+
 // Master weights -> BF16 [co_pad][K] and the flipped transpose
 // Wt[ci][tap' co8 + c] = W[c][tap ci + ci] with tap' the mirrored tap.
 __global__ void k_weight_prep(const float *w32, int co, int ci, int k, bf16 *wb, bf16 *wt, int co_pad, int ci_pad)
@@ -699,6 +735,12 @@ int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co
             if (deep) launch_brick<1, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
             else launch_brick<1, 1, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
         }
+        return status();
+    }
+    const int nout = std::max(y ? y->c : 0, y32 ? y32->c : 0);
+    if (k == 1 && nout <= 4 && x->c <= 64) {
+        hipLaunchKernelGGL(k_conv1_small<4>, dim3(grid_for(P)), dim3(256), 0, (hipStream_t)hip_stream, *x,
+                           (const bf16 *)w, bias, relu, y ? *y : none, y32 ? *y32 : none, accumulate);
         return status();
     }
     const unsigned gx = (unsigned)((P + 64 * FP - 1) / (64 * FP));
