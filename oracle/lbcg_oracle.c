@@ -23,8 +23,8 @@
  *   - recoloring ....................................... Eq. (10)-(12)
  *   - streaming ........................................ text after Eq. (12)
  * Readings where the paper is silent (body force, wetting ghost layer, the
- * parabolas of Eq. (52), zero colour gradient, halfway bounce-back walls) are
- * listed where they are used.
+ * parabolas of Eq. (52), zero colour gradient, halfway bounce-back walls,
+ * moving walls) are listed where they are used.
  *
  * Layout: populations f[(k*19 + i)*N + node], node = x + nx*(y + ny*z).
  */
@@ -55,6 +55,7 @@ typedef struct {
     double grav[3];         /* buoyancy: F += (rho - rho_ref) * grav */
     double rho_ref;
     int improved;           /* 1: Eq. (18) + correction term; 0: Eq. (6), no correction */
+    double wall_u[2][3];    /* velocity of the low / high wall of the wall axis (tangential) */
 } orc_params;
 
 /* ------------------------------------------------------------------ tables */
@@ -368,8 +369,8 @@ static void iso_grad(const lat_t *L, const double *fld, const double *glo, const
  * isotropic stencil (weights 1/9 axis, 1/36 diagonal).  For Qbar (which holds
  * u, zero at the halfway wall) the odd reflection -Qbar of the first layer.
  */
-static void build_ghosts(const lat_t *L, const double *rhoN, const double *qbar,
-                         double *gN_lo, double *gN_hi, double *gQ_lo, double *gQ_hi)
+static void build_ghosts(const lat_t *L, const double *rhoN, const double *qbar, const double *rhoR_l,
+                         const double *rhoB_l, double *gN_lo, double *gN_hi, double *gQ_lo, double *gQ_hi)
 {
     int a = L->wall;
     if (a < 0) return;
@@ -399,7 +400,15 @@ static void build_ghosts(const lat_t *L, const double *rhoN, const double *qbar,
                     }
                 double gpar = sqrt(gb * gb + gc * gc);
                 gN[node] = rhoN[node] + cot[s] * gpar;
-                for (int comp = 0; comp < 6; ++comp) gQ[node * 6 + comp] = -qbar[node * 6 + comp];
+                /* Qbar^k = rho_k u (1 - 3 cs2_k) takes the wall's value half way:
+                 * ghost = 2 Qbar^k(wall) - Qbar^k(first layer), with the wall
+                 * velocity and the first layer's colour densities. */
+                for (int k = 0; k < 2; ++k) {
+                    const double rk = k == 0 ? rhoR_l[node] : rhoB_l[node];
+                    const double qc = 1.0 - 1.5 * (1.0 - p->alpha[k]);
+                    for (int a3 = 0; a3 < 3; ++a3)
+                        gQ[node * 6 + 3 * k + a3] = 2.0 * rk * p->wall_u[s][a3] * qc - qbar[node * 6 + 3 * k + a3];
+                }
             }
     }
 }
@@ -442,7 +451,7 @@ static void stencil_fields(const lat_t *L, const double *f, double *rhoR, double
             for (int c = 0; c < 3; ++c)
                 qbar[6 * n + 3 * k + c] = r[k] * u[3 * n + c] * (1.0 - 3.0 * cs2_k(p, k));
     }
-    build_ghosts(L, rhoN, qbar, gN_lo, gN_hi, gQ_lo, gQ_hi);
+    build_ghosts(L, rhoN, qbar, rhoR, rhoB, gN_lo, gN_hi, gQ_lo, gQ_hi);
     #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < L->N; ++n) {
         int c[3] = {(int)(n % L->n[0]), (int)((n / L->n[0]) % L->n[1]), (int)(n / ((int64_t)L->n[0] * L->n[1]))};
@@ -488,22 +497,30 @@ static void work_free(work_t *w)
 }
 
 /* Pull source of direction i at node c: (source node, source direction).
- * Periodic wrap, or halfway bounce-back when x - e_i lies beyond a wall. */
-static void pull_source(const lat_t *L, const int c[3], int i, int64_t *src, int *dir)
+ * Periodic wrap, or halfway bounce-back when x - e_i lies beyond a wall.
+ * *side (optional) is -1 without bounce-back, else 0 / 1 for the low / high wall. */
+static void pull_source_side(const lat_t *L, const int c[3], int i, int64_t *src, int *dir, int *side)
 {
     int e[3] = {EX[i], EY[i], EZ[i]};
     int q[3];
+    if (side) *side = -1;
     for (int a = 0; a < 3; ++a) {
         int v = c[a] - e[a];
         if (a == L->wall && (v < 0 || v >= L->n[a])) {
             *src = idx(L, c);
             *dir = OPP[i];
+            if (side) *side = v < 0 ? 0 : 1;
             return;
         }
         q[a] = wrap(v, L->n[a]);
     }
     *src = idx(L, q);
     *dir = i;
+}
+
+static void pull_source(const lat_t *L, const int c[3], int i, int64_t *src, int *dir)
+{
+    pull_source_side(L, c, i, src, dir, NULL);
 }
 
 /* One time step t -> t+1: collide + perturb + recolor at every node, then stream. */
@@ -537,10 +554,22 @@ static void one_step(const lat_t *L, const double *f, double *fnext, work_t *w)
     for (int64_t n = 0; n < N; ++n) {
         int c[3] = {(int)(n % L->n[0]), (int)((n / L->n[0]) % L->n[1]), (int)(n / ((int64_t)L->n[0] * L->n[1]))};
         for (int i = 0; i < Q; ++i) {
-            int64_t src; int dir;
-            pull_source(L, c, i, &src, &dir);
-            for (int k = 0; k < 2; ++k)
-                fnext[(int64_t)(k * Q + i) * N + n] = w->fpost[(int64_t)(k * Q + dir) * N + src];
+            int64_t src; int dir, side;
+            pull_source_side(L, c, i, &src, &dir, &side);
+            for (int k = 0; k < 2; ++k) {
+                double v = w->fpost[(int64_t)(k * Q + dir) * N + src];
+                /* Moving halfway wall (reading; the paper uses moving plates in
+                 * Sec. IV.A): the reflected population of colour k gains the
+                 * momentum of a wall moving at U_w, 2 w_i rho_k (e_i . U_w) / c_s^2,
+                 * with c_s^2 = 1/3 of the w_i-weighted first-order equilibrium
+                 * term and rho_k this node's colour density. */
+                if (side >= 0) {
+                    const double *uw = p->wall_u[side];
+                    const double eu = EX[i] * uw[0] + EY[i] * uw[1] + EZ[i] * uw[2];
+                    v += 6.0 * W[i] * (k == 0 ? w->rhoR[n] : w->rhoB[n]) * eu;
+                }
+                fnext[(int64_t)(k * Q + i) * N + n] = v;
+            }
         }
     }
 }

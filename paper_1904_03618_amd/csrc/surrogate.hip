@@ -673,6 +673,30 @@ __global__ void k_pack(const float *f, int nf, int nx, int ny, int nz, int x0, i
     }
 }
 
+// Position-per-lane form of k_pack for an 8-channel BF16 view (the network
+// input): the nf planar fields are read coalesced, one 16-byte BF16 row and
+// (optionally) the FP32 row are written per position.
+__global__ void k_pack8(const float *f, int nf, int nx, int ny, int nz, int x0, int y0, int z0, sg_view y, sg_view y32,
+                        int b, Scale sc)
+{
+    const int64_t per = (int64_t)y.d * y.h * y.w;
+    const int64_t nxyz = (int64_t)nx * ny * nz;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < per; p += (int64_t)gridDim.x * blockDim.x) {
+        const int x = (int)(p % y.w), yy = (int)((p / y.w) % y.h), z = (int)(p / ((int64_t)y.w * y.h));
+        const int gx = (x0 + x) % nx, gy = (y0 + yy) % ny, gz = (z0 + z) % nz;
+        const int64_t src = gx + (int64_t)nx * (gy + (int64_t)ny * gz);
+        float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < nf; ++c) v[c] = f[(int64_t)c * nxyz + src] / sc.s[c];
+        bf16x8 o;
+        #pragma unroll
+        for (int j = 0; j < 8; ++j) o[j] = (bf16)v[j];
+        const int64_t pp = (int64_t)b * per + p;
+        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + pp * y.ctot + y.coff) = o;
+        if (y32.p)
+            for (int c = 0; c < y32.c; ++c) reinterpret_cast<float *>(y32.p)[pp * y32.ctot + y32.coff + c] = v[c];
+    }
+}
+
 __global__ void k_unpack(sg_view x, int b, float *f, int nf, Scale sc)
 {
     const int64_t per = (int64_t)x.d * x.h * x.w;
@@ -925,6 +949,12 @@ int sg_pack(const float *f, int32_t nf, int32_t nx, int32_t ny, int32_t nz, int3
         return SG_EINVAL;
     if (y32 && (!ok_view(y32) || !same_pos(y, y32))) return SG_EINVAL;
     const sg_view none = {};
+    if (y->c == 8 && mfma_view(y) && (!y32 || y32->c <= 8)) {
+        const int64_t per = (int64_t)y->d * y->h * y->w;
+        hipLaunchKernelGGL(k_pack8, dim3(grid_for(per)), dim3(256), 0, (hipStream_t)hip_stream, f, nf, nx, ny, nz, x0, y0,
+                           z0, *y, y32 ? *y32 : none, b, sc);
+        return status();
+    }
     const int64_t n = (int64_t)y->d * y->h * y->w * y->c;
     hipLaunchKernelGGL(k_pack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, f, nf, nx, ny, nz, x0, y0, z0,
                        *y, y32 ? *y32 : none, b, sc);
