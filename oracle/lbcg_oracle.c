@@ -559,14 +559,16 @@ static void one_step(const lat_t *L, const double *f, double *fnext, work_t *w)
             for (int k = 0; k < 2; ++k) {
                 double v = w->fpost[(int64_t)(k * Q + dir) * N + src];
                 /* Moving halfway wall (reading; the paper uses moving plates in
-                 * Sec. IV.A): the reflected population of colour k gains the
-                 * momentum of a wall moving at U_w, 2 w_i rho_k (e_i . U_w) / c_s^2,
-                 * with c_s^2 = 1/3 of the w_i-weighted first-order equilibrium
-                 * term and rho_k this node's colour density. */
+                 * Sec. IV.A): the reflected population of colour k gains twice
+                 * the odd part of the model's own equilibrium (Eq. 18, or Eq. 6
+                 * for the original model) at the wall velocity U_w,
+                 * f_i^{k,eq}(rho_k, U_w) - f_opp(i)^{k,eq}(rho_k, U_w), with rho_k
+                 * this node's colour density.  A uniform flow at U_w is then a
+                 * fixed point of the wall. */
                 if (side >= 0) {
-                    const double *uw = p->wall_u[side];
-                    const double eu = EX[i] * uw[0] + EY[i] * uw[1] + EZ[i] * uw[2];
-                    v += 6.0 * W[i] * (k == 0 ? w->rhoR[n] : w->rhoB[n]) * eu;
+                    double fw[Q];
+                    feq_k(p, k, k == 0 ? w->rhoR[n] : w->rhoB[n], p->wall_u[side], fw);
+                    v += fw[i] - fw[OPP[i]];
                 }
                 fnext[(int64_t)(k * Q + i) * N + n] = v;
             }
