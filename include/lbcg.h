@@ -65,7 +65,12 @@ extern "C" {
  *   theta_deg contact angle, measured through the red fluid, of the low and
  *             high wall of the wall axis (90 = neutral);
  *   improved  1: improved model (Eq. 18 equilibrium + correction term Eq. 45);
- *             0: the same MRT model without both improvements.
+ *             0: the same MRT model without both improvements;
+ *   wall_u    velocity of the low and high wall of the wall axis (moving
+ *             plates, Sec. IV.A); tangential only (the component along the
+ *             wall axis must be 0) and zero when no axis is a wall.  A
+ *             population reflected at a moving wall gains 2 w_i rho_k
+ *             (e_i . U_w) / c_s^2 (c_s^2 = 1/3), rho_k the node's colour density.
  */
 typedef struct lbcg_case {
     int32_t nx, ny, nz;
@@ -82,6 +87,7 @@ typedef struct lbcg_case {
     double rho_ref;
     int32_t improved;
     int32_t reserved;
+    double wall_u[2][3];
 } lbcg_case;
 
 /* Initial fields of one case: FP64 arrays of nx*ny*nz values, x-fastest.

@@ -151,6 +151,9 @@ struct DevCase {
     float F[3], g[3], rho_ref;   // force density = F + (rho - rho_ref) g
     float cot[2];                // cot(theta) of the low / high wall
     float neg_tol[2];            // stability check: rho_k < neg_tol[k] is unstable
+    float uw[2][3];              // velocity of the low / high wall (tangential)
+    float wg[2][2];              // wall gain per colour for axis / diagonal links, per unit rho_k (e_i . U_w)
+    int moving, pad1;            // 1 when a wall velocity is nonzero
 };
 
 struct StepArgs {
@@ -160,6 +163,7 @@ struct StepArgs {
     float4 *ghost;               // per wall-plane node: same fields one layer beyond the wall
     const float2 *rho_prev;      // rho_R, rho_B the writers of fin stored with their values
     float2 *rho_cur;             // rho_R, rho_B stored with fout
+    float *wallq;                // per ghost entry: sum_k rho_k (1 - 3 c_s^k^2) of the first layer
     const DevCase *cases;
     const int2 *tiles;           // (case, first node) per tile
     int ntiles;

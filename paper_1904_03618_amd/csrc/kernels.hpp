@@ -112,6 +112,26 @@ __device__ inline bool bounce(const Coord &c)
            (Z == 1 && c.lo[2]) || (Z == -1 && c.hi[2]);
 }
 
+// Wall a bounce-back of direction i reflects at: 0 low, 1 high, -1 none.
+template <int I>
+__device__ inline int bounce_side(const Coord &c)
+{
+    constexpr int X = ex(I), Y = ey(I), Z = ez(I);
+    const bool lo = (X == 1 && c.lo[0]) || (Y == 1 && c.lo[1]) || (Z == 1 && c.lo[2]);
+    const bool hi = (X == -1 && c.hi[0]) || (Y == -1 && c.hi[1]) || (Z == -1 && c.hi[2]);
+    return lo ? 0 : (hi ? 1 : -1);
+}
+
+// e_i . U_w of the wall a bounce-back of direction i reflects at.  A
+// reflected population of colour k gains wg[k][class] * rho_k * (e_i . U_w):
+// twice the odd part of the equilibrium at the wall velocity, so that a
+// uniform flow at U_w is left unchanged by the wall.
+template <int I>
+__device__ inline float wall_eu(DC &C, int side)
+{
+    return ex(I) * C.uw[side][0] + ey(I) * C.uw[side][1] + ez(I) * C.uw[side][2];
+}
+
 template <int I>
 __device__ inline void pull_source(DC &, const Coord &c, int &src, int &dir)
 {
@@ -154,8 +174,15 @@ __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const 
     const float dR = S::dec(vr, a.inv_scale);
     const float dB = S::dec(vb, a.inv_scale);
     const float2 ps = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, N * sizeof(float2)), si * 8u);
-    const float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
-    const float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
+    float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
+    float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
+    if constexpr (I != 0) {
+        if (C.moving && bb) {        // moving wall: the reflected population gains its momentum
+            const float eu = wall_eu<I>(C, bounce_side<I>(c));
+            tR = __builtin_fmaf(eu * C.wg[0][ecls(I) - 1], own.x, tR);
+            tB = __builtin_fmaf(eu * C.wg[1][ecls(I) - 1], own.y, tB);
+        }
+    }
     const float h = tR + tB;
     s.h[I] = h;
     eR += tR;
@@ -234,6 +261,15 @@ __global__ __launch_bounds__(256) void k_aux(StepArgs a)
         const Macro m = macro(C, s);
         const float qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
         a.aux[C.node_off + node] = make_float4(phase_field(C, s.R[0], s.R[1]), m.ux * qs, m.uy * qs, m.uz * qs);
+        if (C.moving && (c.lo[C.wall] || c.hi[C.wall])) {
+            // first-layer density factor of Qbar for the ghost layer of a moving wall
+            const int w = C.wall, b = w == 0 ? 1 : 0, cax = w == 2 ? 1 : 2;
+            const int co[3] = {c.x, c.y, c.z};
+            const int n[3] = {C.nx, C.ny, C.nz};
+            const int pi = co[b] + n[b] * co[cax];
+            if (c.lo[w]) a.wallq[C.ghost_off + pi] = qs;
+            if (c.hi[w]) a.wallq[C.ghost_off + C.plane + pi] = qs;
+        }
     }
 }
 
@@ -276,7 +312,11 @@ __global__ __launch_bounds__(256) void k_ghost(StepArgs a, const int2 *gtiles, i
         q[b] = ib; q[cax] = ic;
         const float4 s = a.aux[C.node_off + q[0] + C.nx * (q[1] + C.ny * q[2])];
         const float gpar = sqrtf(gb * gb + gc * gc);
-        a.ghost[C.ghost_off + e] = make_float4(s.x + C.cot[side] * gpar, -s.y, -s.z, -s.w);
+        // Qbar takes the wall's value half way: ghost = 2 Qbar(wall) - Qbar(first
+        // layer), Qbar(wall) = U_w sum_k rho_k (1 - 3 c_s^k^2) of the first layer
+        const float qw = C.moving ? 2.0f * a.wallq[C.ghost_off + e] : 0.f;
+        a.ghost[C.ghost_off + e] = make_float4(s.x + C.cot[side] * gpar, qw * C.uw[side][0] - s.y,
+                                               qw * C.uw[side][1] - s.z, qw * C.uw[side][2] - s.w);
     }
 }
 
@@ -768,9 +808,17 @@ __device__ inline void get_dirs(const StepArgs &a, DC &C, const Coord &c, float 
         const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
         const size_t N = (size_t)C.N;
         const float2 rp = a.rho_prev[C.node_off + src];
-        out[(size_t)I * N + c.node] = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(base[(size_t)dir * N + src], a.inv_scale));
-        out[(size_t)(Q + I) * N + c.node] =
-            __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(base[(size_t)(Q + dir) * N + src], a.inv_scale));
+        float vR = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(base[(size_t)dir * N + src], a.inv_scale));
+        float vB = __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(base[(size_t)(Q + dir) * N + src], a.inv_scale));
+        if constexpr (I != 0) {
+            if (C.moving && dir != I) {   // bounce-back at a moving wall (src is this node)
+                const float eu = wall_eu<I>(C, bounce_side<I>(c));
+                vR = __builtin_fmaf(eu * C.wg[0][ecls(I) - 1], rp.x, vR);
+                vB = __builtin_fmaf(eu * C.wg[1][ecls(I) - 1], rp.y, vB);
+            }
+        }
+        out[(size_t)I * N + c.node] = vR;
+        out[(size_t)(Q + I) * N + c.node] = vB;
         get_dirs<ST, I + 1>(a, C, c, out);
     }
 }
@@ -815,7 +863,13 @@ __device__ inline void init_dirs(const StepArgs &a, DC &C, const Coord &c, const
             if (ic.improved) br += 3.0 * eu * (3.0 * cs2 - 1.0) * (3.0 * cl - 5.0);
             const double fe = r[k] * (ph + w * br);
             const float rs = (float)(k == 0 ? rR0[src] : rB0[src]);
-            const double dev = fe - (double)rs * (double)C.phi[k][cl];
+            double dev = fe - (double)rs * (double)C.phi[k][cl];
+            if constexpr (I != 0) {
+                // a slot the pull reads across a moving wall gets the wall's
+                // momentum added on the way; store the start level without it
+                if (C.moving && dir != I)
+                    dev -= (double)(wall_eu<I>(C, bounce_side<I>(c)) * C.wg[k][ecls(I) - 1]) * (double)rs;
+            }
             base[(size_t)(k * Q + dir) * N + src] = (T)(float)(dev * (double)a.scale);
         }
         init_dirs<ST, I + 1>(a, C, c, ic, r, u, uu, rR0, rB0);

@@ -50,6 +50,7 @@ struct lbcg_handle {
     void *pop[2] = {nullptr, nullptr};
     int cur = 0;                       // pop[cur] holds the current level
     float4 *aux = nullptr, *ghost = nullptr;
+    float *wallq = nullptr;            // per ghost entry: first-layer Qbar density factor (moving walls)
     float2 *rho2[2] = {nullptr, nullptr};
     double *partial = nullptr, *red = nullptr;
     int64_t steps = 0, total_nodes = 0, total_pop = 0, total_ghost = 0;
@@ -106,6 +107,16 @@ int validate(const lbcg_case &c, int idx)
     if (std::fabs(pR - pB) > 1e-12 * std::max(pR, pB))
         return bad("pressure balance rho_R^in (1 - alpha_R) = rho_B^in (1 - alpha_B) violated");
     if (c.improved != 0 && c.improved != 1) return bad("improved must be 0 or 1");
+    int wall_axis = -1;
+    for (int a = 0; a < 3; ++a)
+        if (c.bc[a] == LBCG_WALL) wall_axis = a;
+    for (int sd = 0; sd < 2; ++sd)
+        for (int a = 0; a < 3; ++a) {
+            const double v = c.wall_u[sd][a];
+            if (!std::isfinite(v)) return bad("wall_u must be finite");
+            if (v != 0.0 && wall_axis < 0) return bad("wall_u needs a wall axis");
+            if (v != 0.0 && a == wall_axis) return bad("wall_u must be tangential to the wall");
+        }
     return LBCG_OK;
 }
 
@@ -130,6 +141,11 @@ DevCase derive(const lbcg_case &c)
         d.phi[k][2] = (float)((1.0 - al) / 24.0);
         d.neg_tol[k] = (float)(-1e-3 * c.rho_in[k]);
         d.cot[k] = (float)std::tan((90.0 - c.theta_deg[k]) * M_PI / 180.0);
+        // twice the odd part of f^{k,eq} per unit rho_k (e_i . U): 2 w_i [3 + 3 (3 c_s^2 - 1)(3|e_i|^2 - 5)]
+        // with the third-order term of the improved equilibrium, 2 w_i 3 without it
+        const double ex3 = c.improved ? 3.0 * (3.0 * cs2 - 1.0) : 0.0;
+        d.wg[k][0] = (float)(2.0 / 18.0 * (3.0 - 2.0 * ex3));
+        d.wg[k][1] = (float)(2.0 / 36.0 * (3.0 + ex3));
     }
     const double tR = c.tau_v[0], tB = c.tau_v[1], dl = c.delta;
     const double s1 = 2.0 * tR * tB / (tR + tB), s2 = 2.0 * (tR - s1) / dl, s3 = -s2 / (2.0 * dl);
@@ -142,6 +158,12 @@ DevCase derive(const lbcg_case &c)
     d.beta = (float)c.beta;
     for (int a = 0; a < 3; ++a) { d.F[a] = (float)c.force[a]; d.g[a] = (float)c.grav[a]; }
     d.rho_ref = (float)c.rho_ref;
+    d.moving = 0;
+    for (int sd = 0; sd < 2; ++sd)
+        for (int a = 0; a < 3; ++a) {
+            d.uw[sd][a] = (float)c.wall_u[sd][a];
+            if (c.wall_u[sd][a] != 0.0) d.moving = 1;
+        }
     return d;
 }
 
@@ -152,6 +174,7 @@ StepArgs args_for(const lbcg_handle *h)
     a.fout = h->pop[h->cur ^ 1];
     a.aux = h->aux;
     a.ghost = h->ghost;
+    a.wallq = h->wallq;
     // level t was written with the densities of level t-1 (rho2[(t+1)&1]);
     // the collision of level t records its own densities in rho2[t&1]
     a.rho_prev = h->rho2[(h->steps + 1) & 1];
@@ -317,6 +340,7 @@ void release(lbcg_handle *h)
     (void)hipFree(h->pop[1]);
     (void)hipFree(h->aux);
     (void)hipFree(h->ghost);
+    (void)hipFree(h->wallq);
     (void)hipFree(h->rho2[0]);
     (void)hipFree(h->rho2[1]);
     (void)hipFree(h->partial);
@@ -455,10 +479,11 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     // fused eligibility: walls only on z and neutral there
     bool eligible = true;
     for (const DevCase &d : h->dc)
-        if (d.wall == 0 || d.wall == 1 || (d.wall == 2 && (d.cot[0] != 0.0f || d.cot[1] != 0.0f))) eligible = false;
+        if (d.wall == 0 || d.wall == 1 || (d.wall == 2 && (d.cot[0] != 0.0f || d.cot[1] != 0.0f)) || d.moving)
+            eligible = false;
     if (o.kernel == LBCG_KERNEL_FUSED && !eligible) {
         delete h;
-        return fail(LBCG_EINVAL, "fused kernel needs walls only on z with theta = 90 deg");
+        return fail(LBCG_EINVAL, "fused kernel needs walls only on z, at rest, with theta = 90 deg");
     }
     // The two-pass step is the faster one on gfx950 today (the fused kernel is
     // latency-bound at two waves per SIMD), so AUTO selects it.
@@ -486,6 +511,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
               alloc(&h->pop[1], (size_t)h->elem * h->total_pop) &&
               alloc((void **)&h->aux, sizeof(float4) * h->total_nodes) &&
               alloc((void **)&h->ghost, sizeof(float4) * std::max<int64_t>(1, h->total_ghost)) &&
+              alloc((void **)&h->wallq, sizeof(float) * std::max<int64_t>(1, h->total_ghost)) &&
               alloc((void **)&h->partial, sizeof(double) * 6 * (size_t)h->ntiles) &&
               alloc((void **)&h->red, sizeof(double) * 8) &&
               alloc((void **)&h->d_ftiles, sizeof(int4) * std::max<size_t>(1, ftiles.size()));

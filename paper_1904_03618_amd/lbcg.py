@@ -41,7 +41,8 @@ class lbcg_case(C.Structure):
                 ("beta", C.c_double), ("delta", C.c_double),
                 ("tau_e", C.c_double), ("tau_q", C.c_double), ("tau_pi", C.c_double),
                 ("force", C.c_double * 3), ("grav", C.c_double * 3), ("rho_ref", C.c_double),
-                ("improved", C.c_int32), ("reserved", C.c_int32)]
+                ("improved", C.c_int32), ("reserved", C.c_int32),
+                ("wall_u", (C.c_double * 3) * 2)]
 
 
 class lbcg_fields(C.Structure):
@@ -124,6 +125,9 @@ def pack_case(p: dict) -> lbcg_case:
     for name in ("beta", "delta", "tau_e", "tau_q", "tau_pi", "rho_ref"):
         setattr(c, name, float(p[name]))
     c.improved = int(p["improved"])
+    wu = p.get("wall_u", ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    for side in range(2):
+        c.wall_u[side][:] = [float(v) for v in wu[side]]
     return c
 
 

@@ -9,7 +9,9 @@ these inputs; neither computes them.
 A case is ``(params, fields)``:
   params  plain dict: nx, ny, nz, bc[3] (0 periodic / 1 wall), theta_deg[2],
           rho_in[2], alpha[2], tau_v[2], A[2], beta, delta, tau_e, tau_q,
-          tau_pi, force[3], grav[3], rho_ref, improved
+          tau_pi, force[3], grav[3], rho_ref, improved, wall_u[2][3]
+          (tangential velocity of the wall at the low and the high end of the
+          wall axis)
   fields  dict of float64 arrays of length nx*ny*nz in x-fastest order:
           rhoR, rhoB, ux, uy, uz  (the initial colour densities and velocity)
 
@@ -24,7 +26,7 @@ import numpy as np
 
 DEFAULTS = dict(bc=(0, 0, 0), theta_deg=(90.0, 90.0), beta=0.5, delta=0.98,
                 tau_e=1.0, tau_q=1.0, tau_pi=1.0, force=(0.0, 0.0, 0.0),
-                grav=(0.0, 0.0, 0.0), rho_ref=0.0, improved=1)
+                grav=(0.0, 0.0, 0.0), rho_ref=0.0, improved=1, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
 
 
 def _params(**kw) -> dict:
@@ -138,6 +140,25 @@ def rayleigh_taylor(nx=128, ny=None, nz=None, g=2e-5, Re=1024.0, amp=0.05, rho_i
     h = amp * L * (np.cos(2 * np.pi * x / L) + np.cos(2 * np.pi * y / L))
     red = z >= nz / 2.0 + h
     f = dict(rhoR=np.where(red, rho_in[0], 0.0), rhoB=np.where(red, 0.0, rho_in[1]),
+             ux=np.zeros_like(x), uy=np.zeros_like(x), uz=np.zeros_like(x))
+    return p, f
+
+
+def galilean_plates(nx=140, ny=140, nz=4, radius=30.0, improved=1, U=0.0):
+    """Moving droplet between two plates (Sec. IV.A): walls at y, periodic x
+    and z, a circular (z-invariant) droplet of radius 30 at the centre of the
+    x-y plane, rho^in 3/1, alpha 0.9/0.7, A_R = A_B = 0.01, beta = 0.5,
+    mu_R = mu_B = 0.075.  With (c_s^k)^2 = (1 - alpha_k)/2 both fluids have
+    rho_k^in (c_s^k)^2 = 0.15, so nu_k = (c_s^k)^2 (tau_v^k - 1/2) gives
+    tau_v = 1 for both; the other relaxation times are 1.  Both plates move
+    along x with velocity U (0 while the droplet relaxes at rest)."""
+    p = _params(nx=nx, ny=ny, nz=nz, bc=(0, 1, 0), rho_in=(3.0, 1.0), alpha=(0.9, 0.7),
+                tau_v=(1.0, 1.0), A=(0.01, 0.01), improved=improved,
+                wall_u=((U, 0.0, 0.0), (U, 0.0, 0.0)))
+    x, y, _ = _grid(nx, ny, nz)
+    cx, cy = nx / 2.0 - 0.5, ny / 2.0 - 0.5
+    inside = _periodic_d2(x, cx, nx, True) + (y - cy) ** 2 <= radius * radius
+    f = dict(rhoR=np.where(inside, 3.0, 0.0), rhoB=np.where(inside, 0.0, 1.0),
              ux=np.zeros_like(x), uy=np.zeros_like(x), uz=np.zeros_like(x))
     return p, f
 

@@ -1,6 +1,7 @@
 """Paper-level results computed from macroscopic fields (numpy, any source):
 the Laplace pressure jump of a droplet, the velocity profile of a layered
-channel and the bubble/spike fronts of a Rayleigh-Taylor column.  Used to
+channel, the bubble/spike fronts of a Rayleigh-Taylor column and the shape of
+a z-invariant droplet carried along a periodic x axis.  Used to
 state the error of each storage format against the FP64 oracle."""
 import numpy as np
 
@@ -38,3 +39,34 @@ def fronts(rhoN, p):
         i = int(k[0])
         out.append(i + c[i] / (c[i] - c[i + 1]))
     return tuple(out)
+
+
+def droplet_shape(rhoN, p):
+    """Centre, aspect ratio and inclination of a droplet in the x-y plane.
+
+    The phase fraction (1 + rho^N)/2, clipped to [0, 1] and averaged over z,
+    weights the nodes.  x is periodic: the centre along x is the circular mean
+    of the weights, and distances along x are taken modulo nx.  The aspect
+    ratio is sqrt(l1/l2) of the eigenvalues l1 >= l2 of the weighted second
+    moment tensor (a/b for an ellipse with semi-axes a >= b); the inclination
+    is the angle of the major axis to x, in degrees within (-90, 90]."""
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    w = np.clip(0.5 * (1.0 + np.asarray(rhoN, dtype=np.float64).reshape(nz, ny, nx)), 0.0, 1.0).mean(axis=0)
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    m = w.sum()
+    ang = 2.0 * np.pi * x / nx
+    xc = (np.arctan2((w * np.sin(ang)).sum(), (w * np.cos(ang)).sum()) * nx / (2.0 * np.pi)) % nx
+    yc = float((w * y).sum() / m)
+    dx = x - xc
+    dx = dx - nx * np.round(dx / nx)
+    dy = y - yc
+    ixx, iyy, ixy = (w * dx * dx).sum() / m, (w * dy * dy).sum() / m, (w * dx * dy).sum() / m
+    lam, vec = np.linalg.eigh(np.array([[ixx, ixy], [ixy, iyy]]))
+    major = vec[:, 1]
+    incl = float(np.degrees(np.arctan2(major[1], major[0])))
+    if incl <= -90.0:
+        incl += 180.0
+    elif incl > 90.0:
+        incl -= 180.0
+    return dict(xc=float(xc), yc=yc, aspect=float(np.sqrt(lam[1] / lam[0])), incl=incl)

@@ -30,8 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layout_matches_header():
-    # 6 ints + 10 doubles (5 pairs) + 5 doubles + 7 doubles + 2 ints
-    assert C.sizeof(B.lbcg_case) == 6 * 4 + 10 * 8 + 5 * 8 + 7 * 8 + 2 * 4
+    # 6 ints + 10 doubles (5 pairs) + 5 doubles + 7 doubles + 2 ints + 6 doubles (wall velocities)
+    assert C.sizeof(B.lbcg_case) == 6 * 4 + 10 * 8 + 5 * 8 + 7 * 8 + 2 * 4 + 6 * 8
     assert C.sizeof(B.lbcg_fields) == 5 * 8 + 8
     assert C.sizeof(B.lbcg_options) == 32
 

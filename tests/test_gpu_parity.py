@@ -67,6 +67,31 @@ def test_one_step_matches_oracle(improved, bc):
     assert_parity(f"one_step_{improved}_{bc}", g, o, p, tn=1e-6, tu=1e-7, tr=1e-6)
 
 
+@pytest.mark.parametrize("bc,wall_u", [((0, 0, 1), ((0.03, -0.01, 0.0), (0.0, 0.02, 0.0))),
+                                        ((0, 1, 0), ((0.02, 0.0, 0.01), (-0.01, 0.0, 0.0)))])
+def test_one_step_moving_walls(bc, wall_u):
+    """First step with moving walls: the start level already holds the wall
+    momentum the first pull adds, so one step differs from the oracle by FP32
+    rounding only."""
+    p, fl = W.random_state_case(11, 10, 9, seed=13, bc=bc, theta=(75.0, 110.0))
+    p = dict(p, wall_u=wall_u)
+    for steps in (0, 1):
+        assert_parity(f"moving_{bc}_{steps}", gpu_run([(p, fl)], steps)[0], oracle_run(p, fl, steps), p,
+                      tn=1e-6, tu=1e-7, tr=1e-6)
+
+
+def test_moving_walls_rejected_shapes():
+    """Wall velocities must be tangential and need a wall axis."""
+    from paper_1904_03618_amd import lbcg as B
+    p, fl = W.random_state_case(6, 5, 4, seed=1, bc=(0, 0, 1))
+    for wu in (((0.0, 0.0, 0.01), (0.0, 0.0, 0.0)), ((0.0, 0.0, 0.0), (0.0, 0.0, float("nan")))):
+        with pytest.raises(Exception):
+            B.lbcg_init([(dict(p, wall_u=wu), fl)])
+    p2, fl2 = W.random_state_case(6, 5, 4, seed=1, bc=(0, 0, 0))
+    with pytest.raises(Exception):
+        B.lbcg_init([(dict(p2, wall_u=((0.01, 0.0, 0.0), (0.0, 0.0, 0.0))), fl2)])
+
+
 def _offcentre(case, centre=(16.3, 15.6, 16.2)):
     p, _ = case
     return p, W.droplet_fields(p, centre, 8.0, p["rho_in"])
@@ -84,7 +109,19 @@ def _cases():
         "original_model": lambda: W.random_state_case(12, 10, 9, seed=6, improved=0, bc=(0, 1, 0)),
         "wall_x_buoyancy": lambda: W.random_state_case(11, 9, 8, seed=9, bc=(1, 0, 0), theta=(100.0, 80.0),
                                                        grav=(1e-4, 0, 0), rho_ref=2.0),
+        "moving_walls_y": lambda: _moving(W.random_state_case(12, 11, 10, seed=8, bc=(0, 1, 0), theta=(60.0, 130.0)),
+                                          ((0.03, 0.0, -0.01), (-0.02, 0.0, 0.015))),
+        "moving_walls_z_force": lambda: _moving(W.random_state_case(10, 9, 12, seed=10, bc=(0, 0, 1),
+                                                                    force=(1e-5, 0, 0)),
+                                                ((0.02, 0.01, 0.0), (0.0, -0.03, 0.0))),
+        "moving_wall_x_one_side": lambda: _moving(W.random_state_case(9, 10, 8, seed=11, bc=(1, 0, 0), improved=0),
+                                                  ((0.0, 0.025, 0.01), (0.0, 0.0, 0.0))),
     }
+
+
+def _moving(case, wall_u):
+    p, fl = case
+    return dict(p, wall_u=wall_u), fl
 
 
 @pytest.mark.parametrize("name", list(_cases()))

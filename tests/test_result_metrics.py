@@ -38,3 +38,28 @@ def test_fronts_interpolate_first_crossing():
     i = 5
     assert abs(b - (i + col_b[i] / (col_b[i] - col_b[i + 1]))) < 1e-12 and 5.0 < b < 6.0
     assert 2.0 < s < 3.0
+
+
+def test_droplet_shape_of_a_wrapped_ellipse():
+    """A sharp ellipse (semi-axes 20 and 16, major axis at 30 deg to x) whose
+    centre sits 4.7 nodes from the periodic x edge: the second moments of an
+    ellipse of semi-axes a, b are a^2/4 and b^2/4, so the aspect ratio is
+    a/b = 1.25 up to the staircase of the grid; the centre and angle come back.
+    A circle gives 1."""
+    nx, ny, nz = 140, 120, 2
+    p = dict(nx=nx, ny=ny, nz=nz)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cx, cy, t = 135.3, 60.7, np.radians(30.0)
+    dx = x - cx
+    dx = dx - nx * np.round(dx / nx)
+    dy = y - cy
+    u = dx * np.cos(t) + dy * np.sin(t)
+    v = -dx * np.sin(t) + dy * np.cos(t)
+    rhoN = np.where((u / 20.0) ** 2 + (v / 16.0) ** 2 <= 1.0, 1.0, -1.0).reshape(-1)
+    s = RM.droplet_shape(rhoN, p)
+    assert abs(s["xc"] - cx) < 0.1 and abs(s["yc"] - cy) < 0.1, s
+    assert abs(s["aspect"] - 1.25) < 0.01, s
+    assert abs(s["incl"] - 30.0) < 1.0, s
+    circ = np.where(dx * dx + dy * dy <= 18.0 ** 2, 1.0, -1.0).reshape(-1)
+    c = RM.droplet_shape(circ, p)
+    assert abs(c["aspect"] - 1.0) < 0.005 and abs(c["xc"] - cx) < 0.05, c
