@@ -154,7 +154,9 @@ struct NodeState {
 template <int I>
 constexpr int pair_first() { return I == 0 ? 0 : ((I & 1) ? I : I - 1); }
 
-template <int ST, int I>
+// MV: the launch holds a case with a moving wall (a separate instantiation, so
+// that cases at rest pay nothing for the wall-gain code).
+template <int ST, bool MV, int I>
 __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const float2 own,
                                 NodeState &s, float &eR, float &eB)
 {
@@ -176,7 +178,7 @@ __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const 
     const float2 ps = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, N * sizeof(float2)), si * 8u);
     float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
     float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
-    if constexpr (I != 0) {
+    if constexpr (MV && I != 0) {
         if (C.moving && bb) {        // moving wall: the reflected population gains its momentum
             const float eu = wall_eu<I>(C, bounce_side<I>(c));
             tR = __builtin_fmaf(eu * C.wg[0][ecls(I) - 1], own.x, tR);
@@ -195,24 +197,24 @@ __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const 
     if constexpr (ez(I) == -1) s.jz -= h;
 }
 
-template <int ST, int I = 0>
+template <int ST, bool MV, int I = 0>
 __device__ inline void pull_all(const StepArgs &a, DC &C, const Coord &c, const float2 own,
                                 NodeState &s, float &eR, float &eB)
 {
     if constexpr (I < Q) {
-        pull_one<ST, I>(a, C, c, own, s, eR, eB);
-        pull_all<ST, I + 1>(a, C, c, own, s, eR, eB);
+        pull_one<ST, MV, I>(a, C, c, own, s, eR, eB);
+        pull_all<ST, MV, I + 1>(a, C, c, own, s, eR, eB);
     }
 }
 
-template <int ST>
+template <int ST, bool MV>
 __device__ inline void pull_node(const StepArgs &a, DC &C, const Coord &c, NodeState &s)
 {
     const float2 own = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, (size_t)C.N * sizeof(float2)),
                                                   (uint32_t)c.node * 8u);
     float eR = 0.f, eB = 0.f;
     s.jx = s.jy = s.jz = 0.f;
-    pull_all<ST>(a, C, c, own, s, eR, eB);
+    pull_all<ST, MV>(a, C, c, own, s, eR, eB);
     s.R[0] = own.x + eR;
     s.R[1] = own.y + eB;
     s.D[0] = s.R[0] - own.x;
@@ -246,7 +248,7 @@ __device__ inline float phase_field(DC &C, float rR, float rB)
 }
 
 // ----------------------------------------------------------------- k_aux
-template <int ST>
+template <int ST, bool MV>
 __global__ __launch_bounds__(256) void k_aux(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
@@ -257,11 +259,11 @@ __global__ __launch_bounds__(256) void k_aux(StepArgs a)
         if (node >= C.N) continue;
         const Coord c = make_coord(C, node);
         NodeState s;
-        pull_node<ST>(a, C, c, s);
+        pull_node<ST, MV>(a, C, c, s);
         const Macro m = macro(C, s);
         const float qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
         a.aux[C.node_off + node] = make_float4(phase_field(C, s.R[0], s.R[1]), m.ux * qs, m.uy * qs, m.uz * qs);
-        if (C.moving && (c.lo[C.wall] || c.hi[C.wall])) {
+        if (MV && C.moving && (c.lo[C.wall] || c.hi[C.wall])) {
             // first-layer density factor of Qbar for the ghost layer of a moving wall
             const int w = C.wall, b = w == 0 ? 1 : 0, cax = w == 2 ? 1 : 2;
             const int co[3] = {c.x, c.y, c.z};
@@ -559,7 +561,7 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
 }
 
 // ------------------------------------------------------------- k_collide
-template <int ST>
+template <int ST, bool MV>
 __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
@@ -570,7 +572,7 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         if (node >= C.N) continue;
         const Coord c = make_coord(C, node);
         NodeState s;
-        pull_node<ST>(a, C, c, s);
+        pull_node<ST, MV>(a, C, c, s);
         Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         stencil_acc(a, C, c, st);
         collide_node<ST>(a, C, node, s, st, a.aux[C.node_off + node].x);
@@ -645,7 +647,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
     if (active) {
         const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
         const Coord c = make_coord(C, node);
-        pull_node<ST>(a, C, c, keep);
+        pull_node<ST, false>(a, C, c, keep);
         ring[slot][(tx + 1) + FRX * (ty + 1)] = aux_value(C, keep);
     }
     // halo ring of the active (ax x ay) extent
@@ -661,7 +663,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         y = y < 0 ? y + C.ny : (y >= C.ny ? y - C.ny : y);
         const Coord c = make_coord(C, x + C.nx * (y + C.ny * z));
         NodeState hs;
-        pull_node<ST>(a, C, c, hs);
+        pull_node<ST, false>(a, C, c, hs);
         ring[slot][(rx + 1) + FRX * (ry + 1)] = aux_value(C, hs);
     }
 }
@@ -721,7 +723,7 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, int tile0, float *r
     if (node < C.N) {
         const Coord c = make_coord(C, node);
         NodeState s;
-        pull_node<ST>(a, C, c, s);
+        pull_node<ST, true>(a, C, c, s);
         const Macro m = macro(C, s);
         if (rR) rR[node] = s.R[0];
         if (rB) rB[node] = s.R[1];

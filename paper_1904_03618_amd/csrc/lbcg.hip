@@ -56,6 +56,7 @@ struct lbcg_handle {
     int64_t steps = 0, total_nodes = 0, total_pop = 0, total_ghost = 0;
     float scale = 1.0f, inv_scale = 1.0f;
     bool has_wall = false;
+    bool moving = false;               // some case has a moving wall: step kernels with the wall gain
     bool alive = true;
     // kernel timing (lbcg_timing): event pool and pending (kernel, start, end)
     bool timing = false;
@@ -234,14 +235,20 @@ int launch_step(lbcg_handle *h, hipStream_t st)
         return LBCG_OK;
     }
     const int grid = h->persistent > 0 ? h->persistent : h->ntiles;
-    int rc = timed(h, 0, [&] { hipLaunchKernelGGL(k_aux<ST>, dim3(grid), dim3(h->block), 0, st, a); });
+    int rc = timed(h, 0, [&] {
+        if (h->moving) hipLaunchKernelGGL((k_aux<ST, true>), dim3(grid), dim3(h->block), 0, st, a);
+        else hipLaunchKernelGGL((k_aux<ST, false>), dim3(grid), dim3(h->block), 0, st, a);
+    });
     if (!rc && h->has_wall)
         rc = timed(h, 1, [&] {
             hipLaunchKernelGGL(k_ghost, dim3(std::min(h->ngtiles, 65536)), dim3(256), 0, st, a,
                                (const int2 *)h->d_gtiles, h->ngtiles);
         });
     if (!rc)
-        rc = timed(h, 2, [&] { hipLaunchKernelGGL(k_collide<ST>, dim3(grid), dim3(h->block), 0, st, a); });
+        rc = timed(h, 2, [&] {
+            if (h->moving) hipLaunchKernelGGL((k_collide<ST, true>), dim3(grid), dim3(h->block), 0, st, a);
+            else hipLaunchKernelGGL((k_collide<ST, false>), dim3(grid), dim3(h->block), 0, st, a);
+        });
     if (rc) return rc;
     HIPCHK(hipGetLastError());
     h->cur ^= 1;
@@ -466,6 +473,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         h->total_nodes += d.N;
         h->total_ghost += (int64_t)2 * d.plane;
         if (d.wall >= 0) h->has_wall = true;
+        if (d.moving) h->moving = true;
         h->tile_begin.push_back((int)tiles.size());
         for (int n0 = 0; n0 < d.N; n0 += h->block) tiles.push_back(make_int2(c, n0));
         h->tile_count.push_back((int)tiles.size() - h->tile_begin.back());
