@@ -202,6 +202,32 @@ def impact_case(case: int, seed=1904, lmin=48, lmax=128, A=0.00225, width=1.5):
     return p, f
 
 
+def impact_paper(Re, D0=100.0, nx=300, ny=300, nz=150, U0=0.006, ratio=100.0, alpha_B=0.2, A=0.00225,
+                 width=1.5, visc_ratio=10.0):
+    """Droplet impact of Sec. IV.D: 300 x 300 x 150, walls at z (the droplet's
+    flat surface at the bottom, theta = 90 deg on both), periodic x and y.  A
+    droplet of diameter D0 = 100 touches the bottom wall at the centre of the
+    box and moves down at U0 = 0.006; rho^in 8/0.08 (ratio 100), alpha_B =
+    0.2 and alpha_R from pressure balance, A_R = A_B = 0.00225 (sigma =
+    2(A_R + A_B)/9 = 0.001, We = rho_R U0^2 D0/sigma = 28.8).  Re = rho_R U0
+    D0/mu_R sets tau_R through mu_k = rho_k^in (c_s^k)^2 (tau_k - 1/2); the
+    paper does not give mu_B: the gas takes mu_B = mu_R / visc_ratio (default
+    10; both fluids share rho_k^in (c_s^k)^2, so tau_B - 1/2 =
+    (tau_R - 1/2)/visc_ratio).  The droplet starts with a tanh interface of the
+    given width and its velocity carried by the red fraction."""
+    rho_in = (8.0, 8.0 / ratio)
+    aR = 1.0 - (1.0 - alpha_B) / ratio
+    p_k = rho_in[0] * 0.5 * (1.0 - aR)
+    tau = 0.5 + rho_in[0] * U0 * D0 / (Re * p_k)
+    tau_B = 0.5 + (tau - 0.5) / visc_ratio
+    p = _params(nx=nx, ny=ny, nz=nz, bc=(0, 0, 1), theta_deg=(90.0, 90.0), rho_in=rho_in,
+                alpha=(aR, alpha_B), tau_v=(tau, tau_B), A=(A, A))
+    R = 0.5 * D0
+    f = smooth_droplet_fields(p, (nx / 2.0 - 0.5, ny / 2.0 - 0.5, R), R, rho_in, u_in=(0.0, 0.0, -U0),
+                              width=width)
+    return p, f
+
+
 def impact_batch(ncases=256, seed=1904, lmin=48, lmax=128):
     return [impact_case(c, seed=seed, lmin=lmin, lmax=lmax) for c in range(ncases)]
 

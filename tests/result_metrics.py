@@ -1,7 +1,8 @@
 """Paper-level results computed from macroscopic fields (numpy, any source):
 the Laplace pressure jump of a droplet, the velocity profile of a layered
-channel, the bubble/spike fronts of a Rayleigh-Taylor column and the shape of
-a z-invariant droplet carried along a periodic x axis.  Used to
+channel, the bubble/spike fronts of a Rayleigh-Taylor column, the shape of
+a z-invariant droplet carried along a periodic x axis and the spreading of a
+droplet on the bottom wall.  Used to
 state the error of each storage format against the FP64 oracle."""
 import numpy as np
 
@@ -70,3 +71,23 @@ def droplet_shape(rhoN, p):
     elif incl > 90.0:
         incl -= 180.0
     return dict(xc=float(xc), yc=yc, aspect=float(np.sqrt(lam[1] / lam[0])), incl=incl)
+
+
+def spreading(rhoN, p):
+    """(contact, lateral) diameter of a droplet on the bottom wall (z = 0).
+
+    The phase fraction (1 + rho^N)/2, clipped to [0, 1], gives areas: the
+    contact diameter is 2 sqrt(A/pi) of the fraction summed over the first
+    layer, the lateral diameter the same of the droplet's footprint seen along
+    z (the largest fraction over z at each (x, y))."""
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    ph = np.clip(0.5 * (1.0 + np.asarray(rhoN, dtype=np.float64).reshape(nz, ny, nx)), 0.0, 1.0)
+    contact = 2.0 * np.sqrt(ph[0].sum() / np.pi)
+    lateral = 2.0 * np.sqrt(ph.max(axis=0).sum() / np.pi)
+    return float(contact), float(lateral)
+
+
+def asai_spreading(We, Re):
+    """Maximum spreading factor D_max/D_0 of the Asai et al. correlation
+    quoted in Sec. IV.D: 1 + 0.48 We^0.5 exp(-1.48 We^0.22 Re^-0.21)."""
+    return 1.0 + 0.48 * We ** 0.5 * np.exp(-1.48 * We ** 0.22 * Re ** -0.21)

@@ -63,3 +63,28 @@ def test_droplet_shape_of_a_wrapped_ellipse():
     circ = np.where(dx * dx + dy * dy <= 18.0 ** 2, 1.0, -1.0).reshape(-1)
     c = RM.droplet_shape(circ, p)
     assert abs(c["aspect"] - 1.0) < 0.005 and abs(c["xc"] - cx) < 0.05, c
+
+
+def test_spreading_diameters():
+    """A sharp lamella (disk of radius 40, two layers thick) under a
+    hemisphere of radius 25: contact and lateral diameter 80.  A sphere of
+    radius 20 resting on the wall: lateral diameter 40, contact only its
+    lowest nodes.  Grid staircase below 1 %."""
+    nx, ny, nz = 120, 110, 60
+    p = dict(nx=nx, ny=ny, nz=nz)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (x - 60.3) ** 2 + (y - 54.6) ** 2
+    drop = ((r2 <= 40.0 ** 2) & (z < 2)) | (r2 + z ** 2 <= 25.0 ** 2)
+    c, l = RM.spreading(np.where(drop, 1.0, -1.0).reshape(-1), p)
+    assert abs(c / 80.0 - 1.0) < 0.01 and abs(l / 80.0 - 1.0) < 0.01, (c, l)
+    ball = r2 + (z - 20.0) ** 2 <= 20.0 ** 2
+    c, l = RM.spreading(np.where(ball, 1.0, -1.0).reshape(-1), p)
+    assert abs(l / 40.0 - 1.0) < 0.01 and c < 10.0, (c, l)
+
+
+def test_asai_correlation_values():
+    """The correlation at We = 28.8 (the paper's impact): D_max/D_0 rises from
+    1.74 at Re = 75 to 2.25 at Re = 1000 (hand-evaluated: We^0.5 = 5.367,
+    We^0.22 = 2.094, Re^-0.21 = 0.404 and 0.234)."""
+    assert abs(RM.asai_spreading(28.8, 75.0) - 1.7366) < 1e-3
+    assert abs(RM.asai_spreading(28.8, 1000.0) - 2.2455) < 1e-3
