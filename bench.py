@@ -196,7 +196,8 @@ def surrogate_bench(with_rt):
         res["rt_hybrid"] = {
             "lattice": rt["lattice"], "jump_steps": rt["every"], "heal_steps": rt["heal"], "steps": rt["steps"],
             "train_amps": rt["train_amps"], "val_amp": rt["val_amp"], "eval_amp": rt["eval_amp"],
-            "train_iters": rt["train_iters"], "selected_after": rt["selected_after"], "validation": rt["validation"],
+            "train_iters": rt["train_iters"], "seeds": rt["seeds"], "selected_seed": rt["selected_seed"],
+            "selected_after": rt["selected_after"], "validation": rt["validation"],
             "train_s": rt["train_s"], "loss_first": rt["loss_first"],
             "loss_last": rt["loss_last"], "gate_lu": 1.0, "accepted": g["accepted"], "jumps": g["jumps"],
             "max_accepted_front_error": g["max_accepted_error"], "final_front_error": g["final_front_error"],

@@ -232,13 +232,14 @@ def hybrid(net, p, fl, ref_fronts, every, t_start, t_end, heal=20, gate=1.0, use
 
 def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, val_amp=0.045,
                iters=3000, segments=6, heal=20, rec=20, batch=4, slab=None, t_start=None, lr=1e-3, lr_min=1e-5,
-               gates=(1.0, 0.5), log=None):
+               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), log=None):
     """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
     steps apart from snapshots every `rec` steps) in `segments` pieces of one
-    cosine schedule; after each piece the gated hybrid runs on a validation
-    amplitude (val_amp, neither trained on nor evaluated) and the best weights
-    by `score` are kept.  On the held-out amplitude eval_amp, run the gated
-    hybrid at each gate, the same gate with persistence in place of the
+    cosine schedule, once per seed (initial weights and pair sampling); after
+    each piece the gated hybrid runs on a validation amplitude (val_amp,
+    neither trained on nor evaluated) and the best weights over all seeds and
+    pieces by `score` are kept.  On the held-out amplitude eval_amp, run the
+    gated hybrid at each gate, the same gate with persistence in place of the
     network, and the plain LB run.  Returns a summary."""
     import math
     import torch
@@ -260,25 +261,30 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     p, fl = case(L, eval_amp)
     box = (p["nx"], p["ny"], p["nz"])
     ref = reference(p, fl, steps, stride)
-    net = S.UNet((batch, slab or p["nz"], p["ny"], p["nx"]), seed=7, us=0.02, pmask=3)
     full = S.UNet((1, p["nz"], p["ny"], p["nx"]), seed=0, us=0.02, pmask=3)
     torch.cuda.synchronize()
     t0 = time.time()
     hist, best, val = [], None, []
     per_seg = max(1, iters // max(1, segments))
-    for seg in range(max(1, segments)):
-        n_it = per_seg if seg < segments - 1 else iters - per_seg * (segments - 1)
-        hist += train(net, trajs, box, every // rec, iters=n_it, lr=lr, lr_min=lr_min, it0=seg * per_seg, total=iters,
-                      log=log)
-        full.load_state(net.state_dict())
-        hv = hybrid(full, pv, flv, ref_val, every, t_start, steps, heal=heal, gate=1.0)
-        key = score(hv)
-        val.append(dict(iters=seg * per_seg + n_it, accepted=hv["accepted"], final_front_error=hv["final_front_error"]))
-        if log:
-            log(f"validation after {val[-1]['iters']} iterations: accepted {hv['accepted']}/{hv['jumps']}, "
-                f"final front error {hv['final_front_error']:.3f}")
-        if best is None or key > best[0]:
-            best = (key, net.state_dict(), seg)
+    for sd in seeds:
+        net = S.UNet((batch, slab or p["nz"], p["ny"], p["nx"]), seed=sd, us=0.02, pmask=3)
+        hs = []
+        for seg in range(max(1, segments)):
+            n_it = per_seg if seg < segments - 1 else iters - per_seg * (segments - 1)
+            hs += train(net, trajs, box, every // rec, iters=n_it, lr=lr, lr_min=lr_min, seed=sd, it0=seg * per_seg,
+                        total=iters, log=log)
+            full.load_state(net.state_dict())
+            hv = hybrid(full, pv, flv, ref_val, every, t_start, steps, heal=heal, gate=1.0)
+            key = score(hv)
+            val.append(dict(seed=sd, iters=seg * per_seg + n_it, accepted=hv["accepted"],
+                            final_front_error=hv["final_front_error"]))
+            if log:
+                log(f"validation seed {sd} after {val[-1]['iters']} iterations: accepted "
+                    f"{hv['accepted']}/{hv['jumps']}, final front error {hv['final_front_error']:.3f}")
+            if best is None or key > best[0]:
+                best = (key, net.state_dict(), len(val) - 1)
+        if not hist or hs[-1][1] < hist[-1][1]:
+            hist = hs
     torch.cuda.synchronize()
     train_s = time.time() - t0
     del trajs
@@ -287,7 +293,8 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     res = dict(lattice=[p["nx"], p["ny"], p["nz"]], every=every, steps=steps, t_start=t_start, heal=heal,
                train_amps=list(train_amps), val_amp=val_amp, eval_amp=eval_amp, params=net.nparams, train_iters=iters,
                batch=batch, train_shape=list(net.shape), snapshot_every=rec, train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]),
-               validation=val, selected_after=val[best[2]]["iters"], lb_s=lb, trajectory_s=gen, gates={})
+               seeds=list(seeds), validation=val, selected_after=val[best[2]]["iters"],
+               selected_seed=val[best[2]]["seed"], lb_s=lb, trajectory_s=gen, gates={})
     for g in gates:
         hyb = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g)
         per = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g, use_net=False)
@@ -318,10 +325,12 @@ def main(argv=None):
     ap.add_argument("--rec", type=int, default=20, help="snapshot interval of the training trajectories")
     ap.add_argument("--slab", type=int, default=0, help="train on z-slabs of this depth (0: whole box)")
     ap.add_argument("--segments", type=int, default=6)
+    ap.add_argument("--seeds", default="7,8,9,10,11,12", help="training seeds; the validation picks across all of them")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
     res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, rec=a.rec, slab=a.slab or None,
-                     segments=a.segments, log=lambda m: print(m, flush=True))
+                     segments=a.segments, seeds=tuple(int(v) for v in a.seeds.split(",")),
+                     log=lambda m: print(m, flush=True))
     txt = json.dumps(res)
     print(txt, flush=True)
     if a.out:
