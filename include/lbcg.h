@@ -104,7 +104,7 @@ typedef struct lbcg_fields {
 #define LBCG_KERNEL_TWOPASS 1   /* moments pass + collision pass (any boundaries) */
 #define LBCG_KERNEL_FUSED 2     /* single pass, z-marching tiles with an LDS halo;
                                    eligible cases: walls only on z, and those
-                                   walls neutral (theta = 90 deg) */
+                                   walls neutral (theta = 90 deg) and at rest */
 
 /* Handle-wide options.  storage: LBCG_FP32 / LBCG_FP16S / LBCG_BF16S.
  * diag_every: run the stability check every this many steps inside

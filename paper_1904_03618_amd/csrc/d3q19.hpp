@@ -137,7 +137,8 @@ __device__ inline void st_stream(T *p, T v)
 struct DevCase {
     int nx, ny, nz, wall;        // wall: -1 none, else the wall axis
     int N, plane;                // nodes; nodes of one wall plane
-    int improved, pad0;
+    int improved;
+    int NS;                      // stride of the population arrays: N rounded up to 64 nodes
     int64_t pop_off;             // first population element of the case
     int64_t node_off;            // first node of the case in per-node arrays
     int64_t ghost_off;           // first ghost entry (2 planes) of the case

@@ -156,23 +156,23 @@ constexpr int pair_first() { return I == 0 ? 0 : ((I & 1) ? I : I - 1); }
 
 // MV: the launch holds a case with a moving wall (a separate instantiation, so
 // that cases at rest pay nothing for the wall-gain code).
-template <int ST, bool MV, int I>
+template <int ST, bool MV, int CPP, int I>
 __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const float2 own,
                                 NodeState &s, float &eR, float &eB)
 {
     using S = Storage<ST>;
     using T = typename S::T;
     constexpr int F = pair_first<I>(), W = I == 0 ? 1 : 2;
-    const size_t N = (size_t)C.N;
+    const size_t N = (size_t)C.N, NS = (size_t)C.NS;
     const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
     const bool bb = bounce<I>(c);
     const uint32_t si = (uint32_t)(bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c));
     constexpr bool hi_own = I != F, hi_opp = opp(I) != F;          // second array of the pair?
     const bool hi = bb ? hi_opp : hi_own;
-    const uint32_t e = si + (hi ? (uint32_t)N : 0u);
+    const uint32_t e = si + (hi ? (uint32_t)NS : 0u);
     const uint32_t off = e * (uint32_t)sizeof(T);
-    const T vr = buf_ld<T, CP_STREAM>(rsrc(base + (size_t)F * N, W * N * sizeof(T)), off);
-    const T vb = buf_ld<T, CP_STREAM>(rsrc(base + (size_t)(Q + F) * N, W * N * sizeof(T)), off);
+    const T vr = buf_ld<T, CPP>(rsrc(base + (size_t)F * NS, W * NS * sizeof(T)), off);
+    const T vb = buf_ld<T, CPP>(rsrc(base + (size_t)(Q + F) * NS, W * NS * sizeof(T)), off);
     const float dR = S::dec(vr, a.inv_scale);
     const float dB = S::dec(vb, a.inv_scale);
     const float2 ps = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, N * sizeof(float2)), si * 8u);
@@ -197,24 +197,26 @@ __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const 
     if constexpr (ez(I) == -1) s.jz -= h;
 }
 
-template <int ST, bool MV, int I = 0>
+template <int ST, bool MV, int CPP, int I = 0>
 __device__ inline void pull_all(const StepArgs &a, DC &C, const Coord &c, const float2 own,
                                 NodeState &s, float &eR, float &eB)
 {
     if constexpr (I < Q) {
-        pull_one<ST, MV, I>(a, C, c, own, s, eR, eB);
-        pull_all<ST, MV, I + 1>(a, C, c, own, s, eR, eB);
+        pull_one<ST, MV, CPP, I>(a, C, c, own, s, eR, eB);
+        pull_all<ST, MV, CPP, I + 1>(a, C, c, own, s, eR, eB);
     }
 }
 
-template <int ST, bool MV>
+// CPP: cache policy of the population loads (streaming unless the same
+// populations are read again soon).
+template <int ST, bool MV, int CPP = CP_STREAM>
 __device__ inline void pull_node(const StepArgs &a, DC &C, const Coord &c, NodeState &s)
 {
     const float2 own = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, (size_t)C.N * sizeof(float2)),
                                                   (uint32_t)c.node * 8u);
     float eR = 0.f, eB = 0.f;
     s.jx = s.jy = s.jz = 0.f;
-    pull_all<ST, MV>(a, C, c, own, s, eR, eB);
+    pull_all<ST, MV, CPP>(a, C, c, own, s, eR, eB);
     s.R[0] = own.x + eR;
     s.R[1] = own.y + eB;
     s.D[0] = s.R[0] - own.x;
@@ -546,15 +548,15 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     seg[15] = sd * (ny + nz); seg[16] = -seg[15]; seg[17] = sd * (ny - nz); seg[18] = -seg[17];
 
     T *outb = reinterpret_cast<T *>(a.fout) + C.pop_off;
-    const size_t N = (size_t)C.N;
+    const size_t N = (size_t)C.N, NS = (size_t)C.NS;
     #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
         const float db = fs[i] - dr;
-        const uint64_t nb = N * sizeof(T);
+        const uint64_t nb = NS * sizeof(T);
         const uint32_t off = (uint32_t)node * (uint32_t)sizeof(T);
-        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)i * N, nb), off, S::enc(dr, a.scale));
-        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)(Q + i) * N, nb), off, S::enc(db, a.scale));
+        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)i * NS, nb), off, S::enc(dr, a.scale));
+        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)(Q + i) * NS, nb), off, S::enc(db, a.scale));
     }
     buf_st<float2, CP_DEFAULT>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u,
                                make_float2(RR, RB));
@@ -582,13 +584,15 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 // ---------------------------------------------------------------- k_fused
 // Single-pass step.  A workgroup owns an FTX x FTY column of nodes over a
 // chunk of z-planes and marches up the chunk.  For each plane it pulls the
-// populations of the tile and of its one-node x-y halo, writes their aux values
-// (rho^N, Qbar) into a three-plane LDS ring, and then collides the plane below
-// from registers with the colour-gradient and correction stencils read from
-// LDS.  Populations are read once per plane plus the halo ring and the two
-// extra planes of each chunk; aux never goes to HBM.  Eligible cases: walls
-// (if any) on z with neutral wetting (cot theta = 0), where the ghost layer is
-// the mirror of the first layer with Qbar reflected oddly.
+// populations of the tile and of its one-node x-y halo and writes their aux
+// values (rho^N, Qbar) into a three-plane LDS ring; then it collides the plane
+// below with the colour-gradient and correction stencils read from LDS.  No
+// node state is held across the plane barrier: the aux pass pulls with
+// cacheable loads and the collision pulls the same populations again one plane
+// later, from L2 or the last-level cache, so register use stays that of the
+// collision pass.  Aux never goes to HBM.  Eligible cases: walls (if any) on z
+// with neutral wetting (cot theta = 0), where the ghost layer is the mirror of
+// the first layer with Qbar reflected oddly.
 constexpr int FTX = 16, FTY = 16;
 constexpr int FRX = FTX + 2, FRY = FTY + 2, FREG = FRX * FRY;
 
@@ -623,48 +627,34 @@ __device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int r, Stencil &
     }
 }
 
-// Fill ring slot of plane zz (-1 <= zz <= nz): pull the tile (keeping the
-// interior state in `keep`) and the halo, or mirror the first layer beyond a
-// wall.
+// Aux values of plane zz (-1 <= zz <= nz) for the tile and its halo, or the
+// mirror of the first layer beyond a wall.
 template <int ST>
-__device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], int zz, int x0,
-                                   int y0, int ax, int ay, bool active, int tx, int ty, NodeState &keep)
+__device__ inline void aux_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], int zz, int x0, int y0,
+                                 int ax, int ay)
 {
     const int slot = ring_slot(zz);
     const int tid = (int)threadIdx.x;
-    const int nreg = (ax + 2) * (ay + 2);
+    const int w = ax + 2, nreg = w * (ay + 2);
     if (C.wall == 2 && (zz < 0 || zz >= C.nz)) {
         const int from = ring_slot(zz < 0 ? 0 : C.nz - 1);
         for (int e = tid; e < nreg; e += blockDim.x) {
-            const int rx = e % (ax + 2), ry = e / (ax + 2);
-            const int r = rx + FRX * ry;
+            const int r = e % w + FRX * (e / w);
             const float4 v = ring[from][r];
             ring[slot][r] = make_float4(v.x, -v.y, -v.z, -v.w);
         }
         return;
     }
     const int z = zz < 0 ? zz + C.nz : (zz >= C.nz ? zz - C.nz : zz);
-    if (active) {
-        const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
-        const Coord c = make_coord(C, node);
-        pull_node<ST, false>(a, C, c, keep);
-        ring[slot][(tx + 1) + FRX * (ty + 1)] = aux_value(C, keep);
-    }
-    // halo ring of the active (ax x ay) extent
-    const int nh = 2 * (ax + 2) + 2 * ay;
-    for (int h = tid; h < nh; h += blockDim.x) {
-        int rx, ry;
-        if (h < ax + 2) { rx = h - 1; ry = -1; }
-        else if (h < 2 * (ax + 2)) { rx = h - (ax + 2) - 1; ry = ay; }
-        else if (h < 2 * (ax + 2) + ay) { rx = -1; ry = h - 2 * (ax + 2); }
-        else { rx = ax; ry = h - 2 * (ax + 2) - ay; }
-        int x = x0 + rx, y = y0 + ry;
+    for (int e = tid; e < nreg; e += blockDim.x) {
+        const int rx = e % w, ry = e / w;
+        int x = x0 + rx - 1, y = y0 + ry - 1;
         x = x < 0 ? x + C.nx : (x >= C.nx ? x - C.nx : x);
         y = y < 0 ? y + C.ny : (y >= C.ny ? y - C.ny : y);
         const Coord c = make_coord(C, x + C.nx * (y + C.ny * z));
-        NodeState hs;
-        pull_node<ST, false>(a, C, c, hs);
-        ring[slot][(rx + 1) + FRX * (ry + 1)] = aux_value(C, hs);
+        NodeState s;
+        pull_node<ST, false, CP_DEFAULT>(a, C, c, s);
+        ring[slot][rx + FRX * ry] = aux_value(C, s);
     }
 }
 
@@ -683,27 +673,27 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
         const int ax = min(FTX, C.nx - x0), ay = min(FTY, C.ny - y0);
         const bool active = tx < ax && ty < ay;
         const int r = (tx + 1) + FRX * (ty + 1);
-        NodeState cur, nxt;
         __syncthreads();                       // ring reuse across tiles
         if (C.wall == 2 && z0 == 0) {
-            fused_plane<ST>(a, C, ring, 0, x0, y0, ax, ay, active, tx, ty, cur);
+            aux_plane<ST>(a, C, ring, 0, x0, y0, ax, ay);
             __syncthreads();
-            fused_plane<ST>(a, C, ring, -1, x0, y0, ax, ay, active, tx, ty, nxt);
+            aux_plane<ST>(a, C, ring, -1, x0, y0, ax, ay);
         } else {
-            fused_plane<ST>(a, C, ring, z0 - 1, x0, y0, ax, ay, active, tx, ty, nxt);
-            fused_plane<ST>(a, C, ring, z0, x0, y0, ax, ay, active, tx, ty, cur);
+            aux_plane<ST>(a, C, ring, z0 - 1, x0, y0, ax, ay);
+            aux_plane<ST>(a, C, ring, z0, x0, y0, ax, ay);
         }
         for (int z = z0; z < z1; ++z) {
-            fused_plane<ST>(a, C, ring, z + 1, x0, y0, ax, ay, active, tx, ty, nxt);
+            aux_plane<ST>(a, C, ring, z + 1, x0, y0, ax, ay);
             __syncthreads();
             if (active) {
+                const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
+                NodeState s;
+                pull_node<ST, false>(a, C, make_coord(C, node), s);
                 Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 stencil_lds(ring, z, r, st);
-                const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
-                collide_node<ST>(a, C, node, cur, st, ring[ring_slot(z)][r].x);
+                collide_node<ST>(a, C, node, s, st, ring[ring_slot(z)][r].x);
             }
             __syncthreads();
-            cur = nxt;
         }
     }
 }
@@ -808,10 +798,10 @@ __device__ inline void get_dirs(const StepArgs &a, DC &C, const Coord &c, float 
         int src, dir;
         pull_source<I>(C, c, src, dir);
         const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
-        const size_t N = (size_t)C.N;
+        const size_t N = (size_t)C.N, NS = (size_t)C.NS;
         const float2 rp = a.rho_prev[C.node_off + src];
-        float vR = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(base[(size_t)dir * N + src], a.inv_scale));
-        float vB = __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(base[(size_t)(Q + dir) * N + src], a.inv_scale));
+        float vR = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(base[(size_t)dir * NS + src], a.inv_scale));
+        float vB = __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(base[(size_t)(Q + dir) * NS + src], a.inv_scale));
         if constexpr (I != 0) {
             if (C.moving && dir != I) {   // bounce-back at a moving wall (src is this node)
                 const float eu = wall_eu<I>(C, bounce_side<I>(c));
@@ -853,7 +843,7 @@ __device__ inline void init_dirs(const StepArgs &a, DC &C, const Coord &c, const
         int src, dir;
         pull_source<I>(C, c, src, dir);
         T *base = reinterpret_cast<T *>(a.fout) + C.pop_off;
-        const size_t N = (size_t)C.N;
+        const size_t NS = (size_t)C.NS;
         const double eu = ex(I) * u[0] + ey(I) * u[1] + ez(I) * u[2];
         const double w = cl == 0 ? 1.0 / 3.0 : (cl == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
         #pragma unroll
@@ -872,7 +862,7 @@ __device__ inline void init_dirs(const StepArgs &a, DC &C, const Coord &c, const
                 if (C.moving && dir != I)
                     dev -= (double)(wall_eu<I>(C, bounce_side<I>(c)) * C.wg[k][ecls(I) - 1]) * (double)rs;
             }
-            base[(size_t)(k * Q + dir) * N + src] = (T)(float)(dev * (double)a.scale);
+            base[(size_t)(k * Q + dir) * NS + src] = (T)(float)(dev * (double)a.scale);
         }
         init_dirs<ST, I + 1>(a, C, c, ic, r, u, uu, rR0, rB0);
     }

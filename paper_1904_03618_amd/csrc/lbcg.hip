@@ -130,6 +130,7 @@ DevCase derive(const lbcg_case &c)
     for (int a = 0; a < 3; ++a)
         if (c.bc[a] == LBCG_WALL) d.wall = a;
     d.N = c.nx * c.ny * c.nz;
+    d.NS = (d.N + 63) / 64 * 64;      // every array of a case starts on a 128-byte boundary (64 FP16 values)
     d.plane = d.wall < 0 ? 0 : d.N / (d.wall == 0 ? c.nx : (d.wall == 1 ? c.ny : c.nz));
     d.improved = c.improved;
     for (int k = 0; k < 2; ++k) {
@@ -469,8 +470,8 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         d.pop_off = h->total_pop;
         d.node_off = h->total_nodes;
         d.ghost_off = h->total_ghost;
-        h->total_pop += (int64_t)2 * Q * d.N;
-        h->total_nodes += d.N;
+        h->total_pop += (int64_t)2 * Q * d.NS;
+        h->total_nodes += d.NS;
         h->total_ghost += (int64_t)2 * d.plane;
         if (d.wall >= 0) h->has_wall = true;
         if (d.moving) h->moving = true;
@@ -494,7 +495,8 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         return fail(LBCG_EINVAL, "fused kernel needs walls only on z, at rest, with theta = 90 deg");
     }
     // The two-pass step is the faster one on gfx950 today (the fused kernel is
-    // latency-bound at two waves per SIMD), so AUTO selects it.
+    // latency-bound: its barrier-separated phases keep few loads in flight), so
+    // AUTO selects it.
     h->fused = eligible && o.kernel == LBCG_KERNEL_FUSED;
     h->zc = o.zchunk;
     h->graph_steps = o.graph_steps + (o.graph_steps & 1);
@@ -541,6 +543,12 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         (!ftiles.empty() && hipMemcpyAsync(h->d_ftiles, ftiles.data(), sizeof(int4) * ftiles.size(),
                                            hipMemcpyHostToDevice, h->stream) != hipSuccess))
         rc = fail(LBCG_EDEVICE, "table upload failed");
+    // the padding between a case's population arrays is never read; clearing it
+    // keeps checkpoint images a function of the state alone
+    for (int b = 0; b < 2 && rc == LBCG_OK; ++b)
+        if (hipMemsetAsync(h->pop[b], 0, (size_t)h->elem * h->total_pop, h->stream) != hipSuccess ||
+            hipMemsetAsync(h->rho2[b], 0, sizeof(float2) * h->total_nodes, h->stream) != hipSuccess)
+            rc = fail(LBCG_EDEVICE, "buffer clear failed");
     for (int c = 0; c < n_cases && rc == LBCG_OK; ++c) rc = init_any(h, c, cases[c], init[c]);
     if (rc == LBCG_OK && hipStreamSynchronize(h->stream) != hipSuccess)
         rc = fail(LBCG_EDEVICE, "synchronise after init failed");
