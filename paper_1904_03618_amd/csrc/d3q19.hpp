@@ -39,19 +39,26 @@ __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 == 1 ?
 // colour density, kept per node in FP32), scaled by 2^s for FP16.  The node's
 // own stored density plus the small deviations carries the populations with
 // well beyond FP32 resolution, so rounding does not bias the colour masses.
+// The red and blue values of one direction at one node are stored side by
+// side, so one 2-element access moves both colours.
+template <class T> struct Pair { T r, b; };
+
 template <int ST> struct Storage;
 template <> struct Storage<LBCG_FP32> {
     using T = float;
+    using P = Pair<T>;
     __device__ static float dec(T v, float) { return v; }
     __device__ static T enc(float d, float) { return d; }
 };
 template <> struct Storage<LBCG_FP16S> {
     using T = _Float16;
+    using P = Pair<T>;
     __device__ static float dec(T v, float inv_scale) { return (float)v * inv_scale; }
     __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };
 template <> struct Storage<LBCG_BF16S> {
     using T = __bf16;
+    using P = Pair<T>;
     __device__ static float dec(T v, float inv_scale) { return (float)v * inv_scale; }
     __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };

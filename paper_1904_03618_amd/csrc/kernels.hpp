@@ -161,20 +161,18 @@ __device__ inline void pull_one(const StepArgs &a, DC &C, const Coord &c, const 
                                 NodeState &s, float &eR, float &eB)
 {
     using S = Storage<ST>;
-    using T = typename S::T;
+    using P = typename S::P;
     constexpr int F = pair_first<I>(), W = I == 0 ? 1 : 2;
     const size_t N = (size_t)C.N, NS = (size_t)C.NS;
-    const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+    const P *base = reinterpret_cast<const P *>(a.fin) + C.pop_off / 2;
     const bool bb = bounce<I>(c);
     const uint32_t si = (uint32_t)(bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c));
     constexpr bool hi_own = I != F, hi_opp = opp(I) != F;          // second array of the pair?
     const bool hi = bb ? hi_opp : hi_own;
     const uint32_t e = si + (hi ? (uint32_t)NS : 0u);
-    const uint32_t off = e * (uint32_t)sizeof(T);
-    const T vr = buf_ld<T, CPP>(rsrc(base + (size_t)F * NS, W * NS * sizeof(T)), off);
-    const T vb = buf_ld<T, CPP>(rsrc(base + (size_t)(Q + F) * NS, W * NS * sizeof(T)), off);
-    const float dR = S::dec(vr, a.inv_scale);
-    const float dB = S::dec(vb, a.inv_scale);
+    const P v = buf_ld<P, CPP>(rsrc(base + (size_t)F * NS, W * NS * sizeof(P)), e * (uint32_t)sizeof(P));
+    const float dR = S::dec(v.r, a.inv_scale);
+    const float dB = S::dec(v.b, a.inv_scale);
     const float2 ps = buf_ld<float2, CP_DEFAULT>(rsrc(a.rho_prev + C.node_off, N * sizeof(float2)), si * 8u);
     float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
     float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
@@ -547,16 +545,16 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     seg[11] = sd * (nx + nz); seg[12] = -seg[11]; seg[13] = sd * (nx - nz); seg[14] = -seg[13];
     seg[15] = sd * (ny + nz); seg[16] = -seg[15]; seg[17] = sd * (ny - nz); seg[18] = -seg[17];
 
-    T *outb = reinterpret_cast<T *>(a.fout) + C.pop_off;
+    using P = typename S::P;
+    P *outb = reinterpret_cast<P *>(a.fout) + C.pop_off / 2;
     const size_t N = (size_t)C.N, NS = (size_t)C.NS;
     #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
         const float db = fs[i] - dr;
-        const uint64_t nb = NS * sizeof(T);
-        const uint32_t off = (uint32_t)node * (uint32_t)sizeof(T);
-        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)i * NS, nb), off, S::enc(dr, a.scale));
-        buf_st<T, CP_STREAM>(rsrc(outb + (size_t)(Q + i) * NS, nb), off, S::enc(db, a.scale));
+        const uint32_t off = (uint32_t)node * (uint32_t)sizeof(P);
+        buf_st<P, CP_STREAM>(rsrc(outb + (size_t)i * NS, NS * sizeof(P)), off,
+                             P{S::enc(dr, a.scale), S::enc(db, a.scale)});
     }
     buf_st<float2, CP_DEFAULT>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u,
                                make_float2(RR, RB));
@@ -797,11 +795,12 @@ __device__ inline void get_dirs(const StepArgs &a, DC &C, const Coord &c, float 
         using T = typename S::T;
         int src, dir;
         pull_source<I>(C, c, src, dir);
-        const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+        const typename S::P *base = reinterpret_cast<const typename S::P *>(a.fin) + C.pop_off / 2;
         const size_t N = (size_t)C.N, NS = (size_t)C.NS;
         const float2 rp = a.rho_prev[C.node_off + src];
-        float vR = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(base[(size_t)dir * NS + src], a.inv_scale));
-        float vB = __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(base[(size_t)(Q + dir) * NS + src], a.inv_scale));
+        const typename S::P v = base[(size_t)dir * NS + src];
+        float vR = __builtin_fmaf(rp.x, C.phi[0][ecls(I)], S::dec(v.r, a.inv_scale));
+        float vB = __builtin_fmaf(rp.y, C.phi[1][ecls(I)], S::dec(v.b, a.inv_scale));
         if constexpr (I != 0) {
             if (C.moving && dir != I) {   // bounce-back at a moving wall (src is this node)
                 const float eu = wall_eu<I>(C, bounce_side<I>(c));
@@ -862,7 +861,7 @@ __device__ inline void init_dirs(const StepArgs &a, DC &C, const Coord &c, const
                 if (C.moving && dir != I)
                     dev -= (double)(wall_eu<I>(C, bounce_side<I>(c)) * C.wg[k][ecls(I) - 1]) * (double)rs;
             }
-            base[(size_t)(k * Q + dir) * NS + src] = (T)(float)(dev * (double)a.scale);
+            base[((size_t)dir * NS + src) * 2 + k] = (T)(float)(dev * (double)a.scale);
         }
         init_dirs<ST, I + 1>(a, C, c, ic, r, u, uu, rR0, rB0);
     }

@@ -731,7 +731,7 @@ int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes)
     if (!host || bytes < ckpt_bytes(h)) return fail(LBCG_EINVAL, "checkpoint buffer NULL or too small");
     CkptHeader hd;
     std::memcpy(hd.magic, kMagic, 8);
-    hd.version = 1;
+    hd.version = 2;
     hd.storage = h->storage;
     hd.ncases = h->ncases;
     hd.total_pop = h->total_pop;
@@ -754,7 +754,7 @@ int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes)
     if (!host || bytes < (int64_t)sizeof(CkptHeader)) return fail(LBCG_EINVAL, "checkpoint buffer NULL or too small");
     CkptHeader hd;
     std::memcpy(&hd, host, sizeof hd);
-    if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 1) return fail(LBCG_EINVAL, "not a checkpoint image");
+    if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 2) return fail(LBCG_EINVAL, "not a checkpoint image");
     if (hd.storage != h->storage || hd.ncases != h->ncases || hd.total_pop != h->total_pop ||
         hd.total_nodes != h->total_nodes || hd.steps < 0)
         return fail(LBCG_EINVAL, "checkpoint of another case shape or storage format");
