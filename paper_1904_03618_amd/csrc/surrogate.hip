@@ -14,6 +14,7 @@ namespace sg {
 
 typedef __bf16 bf16;
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // One MFMA 16x16x32 step.  Lane l (0..63) supplies A[l % 16][8 (l / 16) + j]
@@ -168,8 +169,10 @@ __global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restr
 // fragments from LDS.  Wave w owns z-planes w ZW .. w ZW + ZW - 1 of the brick
 // (4 ZW rows of 16 positions) and NO blocks of 16 output channels.  Layers with
 // few input channels use ZW = 2, CT = 16: twice the MFMA work per staged halo at
-// the same LDS size.  LDS rows are padded by 16 bytes so that the 16 lanes of a
-// fragment read (consecutive x) fall into different banks.
+// the same LDS size.  A staged position holds CT/8 16-byte chunks; the chunk
+// index is XOR-swizzled with the position's x so that the 16 lanes of a
+// fragment read (consecutive x, one chunk each) cover 256 distinct bytes and
+// fall into different banks without padding.
 constexpr int BX = 16, BY = 4;
 constexpr int HX = BX + 2, HY = BY + 2;
 
@@ -178,7 +181,9 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
                                                      const float *__restrict__ bias, int pmask, int relu, sg_view y,
                                                      sg_view y32, int accumulate)
 {
-    constexpr int BZ = 4 * ZW, HZ = BZ + 2, HP = HX * HY * HZ, LROW = CT + 8, NF = 4 * ZW;
+    constexpr int BZ = 4 * ZW, HZ = BZ + 2, HP = HX * HY * HZ, LROW = CT, NF = 4 * ZW;
+    constexpr int NC = CT / 8, XSPAN = 16 / NC;           // chunks per position; positions per 256 bytes
+    auto swz = [](int hx, int c8) { return c8 ^ ((hx / XSPAN) & (NC - 1)); };
     __shared__ __attribute__((aligned(16))) bf16 halo[HP * LROW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
@@ -204,79 +209,132 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
 
     for (int c0 = 0; c0 < ci; c0 += CT) {
         const int gpt = min(CT, ci - c0) >> 3;           // 8-channel groups per tap in this chunk
-        __syncthreads();                                  // previous chunk's fragment reads are done
-        for (int e = threadIdx.x; e < HP * gpt; e += blockDim.x) {
-            const int hp = e / gpt, c8 = e - hp * gpt;
-            const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
-            int gx = X0 - 1 + hx, gy = Y0 - 1 + hy, gz = Z0 - 1 + hz;
-            bool ok = true;
-            if (gx < 0 || gx >= x.w) {
-                if (pmask & 1) gx = gx < 0 ? gx + x.w : gx - x.w;
-                else ok = false;
-            }
-            if (gy < 0 || gy >= x.h) {
-                if (pmask & 2) gy = gy < 0 ? gy + x.h : gy - x.h;
-                else ok = false;
-            }
-            if (gz < 0 || gz >= x.d) {
-                if (pmask & 4) gz = gz < 0 ? gz + x.d : gz - x.d;
-                else ok = false;
-            }
-            bf16x8 v = zero;
-            if (ok)
-                v = *reinterpret_cast<const bf16x8 *>(
-                    xp + ((((int64_t)n * x.d + gz) * x.h + gy) * x.w + gx) * x.ctot + c0 + 8 * c8);
-            *reinterpret_cast<bf16x8 *>(&halo[hp * LROW + 8 * c8]) = v;
-        }
-        __syncthreads();
-        const int G = 27 * gpt;
-        for (int kb = 0; kb < (G + 3) >> 2; ++kb) {
-            const int g = (kb << 2) + grp;
-            bf16x8 a[NO], b[NF];
-            #pragma unroll
-            for (int o = 0; o < NO; ++o) a[o] = zero;
-            #pragma unroll
-            for (int i = 0; i < NF; ++i) b[i] = zero;
-            if (g < G) {
-                const int tap = g / gpt, c8 = g - tap * gpt;
-                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-                #pragma unroll
-                for (int o = 0; o < NO; ++o)
-                    a[o] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * o * K + tap * ci + c0 + 8 * c8);
-                #pragma unroll
-                for (int i = 0; i < NF; ++i) {
-                    const int zl = wave * ZW + i / 4, yl = i % 4;
-                    const int hp = ((zl + 1 + dz) * HY + (yl + 1 + dy)) * HX + (col + 1 + dx);
-                    b[i] = *reinterpret_cast<const bf16x8 *>(&halo[hp * LROW + 8 * c8]);
+        const int lgp = gpt == 1 ? 0 : (gpt == 2 ? 1 : 2);
+        // stage the halo: every load of this thread is issued before the first
+        // LDS store, so the chunk costs one memory latency, not one per element
+        constexpr int PER = (HP * (CT / 8) + 255) / 256;
+        bf16x8 hv[PER];
+        int hdst[PER];
+        #pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = (int)threadIdx.x + 256 * k;
+            hdst[k] = -1;
+            hv[k] = zero;
+            if (e < (HP << lgp)) {
+                const int hp = e >> lgp, c8 = e & (gpt - 1);
+                const int hx = hp % HX, hy = (hp / HX) % HY, hz = hp / (HX * HY);
+                int gx = X0 - 1 + hx, gy = Y0 - 1 + hy, gz = Z0 - 1 + hz;
+                bool ok = true;
+                if (gx < 0 || gx >= x.w) {
+                    if (pmask & 1) gx = gx < 0 ? gx + x.w : gx - x.w;
+                    else ok = false;
                 }
+                if (gy < 0 || gy >= x.h) {
+                    if (pmask & 2) gy = gy < 0 ? gy + x.h : gy - x.h;
+                    else ok = false;
+                }
+                if (gz < 0 || gz >= x.d) {
+                    if (pmask & 4) gz = gz < 0 ? gz + x.d : gz - x.d;
+                    else ok = false;
+                }
+                hdst[k] = hp * LROW + 8 * swz(hx, c8);
+                if (ok)
+                    hv[k] = *reinterpret_cast<const bf16x8 *>(
+                        xp + ((((int64_t)n * x.d + gz) * x.h + gy) * x.w + gx) * x.ctot + c0 + 8 * c8);
             }
+        }
+        __syncthreads();                                  // previous chunk's fragment reads are done
+        #pragma unroll
+        for (int k = 0; k < PER; ++k)
+            if (hdst[k] >= 0) *reinterpret_cast<bf16x8 *>(&halo[hdst[k]]) = hv[k];
+        __syncthreads();
+        // K blocks of 4 (tap, 8-channel group) pairs.  The full blocks run
+        // unmasked; a last partial block (27 gpt not a multiple of 4) zeroes
+        // the weights of its idle lanes.
+        const int G = 27 * gpt, nfull = G >> 2, rem = G & 3, lg = gpt == 1 ? 0 : (gpt == 2 ? 1 : 2);
+        auto fetch = [&](int g, bf16x8 (&a)[NO], bf16x8 (&b)[NF]) {
+            const int tap = g >> lg, c8 = g & (gpt - 1);
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            #pragma unroll
+            for (int o = 0; o < NO; ++o)
+                a[o] = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * o * K + tap * ci + c0 + 8 * c8);
+            #pragma unroll
+            for (int i = 0; i < NF; ++i) {
+                const int zl = wave * ZW + i / 4, yl = i % 4;
+                const int hx = col + 1 + dx;
+                const int hp = ((zl + 1 + dz) * HY + (yl + 1 + dy)) * HX + hx;
+                b[i] = *reinterpret_cast<const bf16x8 *>(&halo[hp * LROW + 8 * swz(hx, c8)]);
+            }
+        };
+        // two register sets in turn, so a block's MFMAs never wait for the
+        // fetch issued after them; the fetch past the end re-reads a valid block
+        auto mma = [&](const bf16x8 (&a)[NO], const bf16x8 (&b)[NF]) {
             #pragma unroll
             for (int o = 0; o < NO; ++o)
                 #pragma unroll
                 for (int i = 0; i < NF; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
+        };
+        bf16x8 a[NO], b[NF], a1[NO], b1[NF];
+        fetch(grp, a, b);
+        int kb = 0;
+        for (; kb + 2 <= nfull; kb += 2) {
+            fetch(((kb + 1) << 2) + grp, a1, b1);
+            mma(a, b);
+            fetch((min(kb + 2, nfull - 1) << 2) + grp, a, b);
+            mma(a1, b1);
         }
-    }
-    #pragma unroll
-    for (int o = 0; o < NO; ++o)
-        #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int oc = co0 + 16 * o + (grp << 2) + j;
-            const bool sy = y.p && oc < y.c, s32 = y32.p && oc < y32.c;
-            if (!sy && !s32) continue;                 // padded output rows
-            const float bo = bias ? bias[oc] : 0.f;
+        if (kb < nfull) mma(a, b);
+        if (rem) {
+            const bool valid = grp < rem;
+            fetch(valid ? (nfull << 2) + grp : G - 1, a, b);
             #pragma unroll
-            for (int i = 0; i < NF; ++i) {
-                const int zl = wave * ZW + i / 4, yl = i % 4;
-                const int64_t pb = (((int64_t)n * x.d + Z0 + zl) * x.h + Y0 + yl) * x.w + X0 + col;
-                float v = acc[o][i][j] + bo;
-                if (relu) v = fmaxf(v, 0.f);
-                if (sy) reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc] = (bf16)v;
-                if (s32) {
-                    float *out = reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc;
-                    *out = accumulate ? *out + v : v;
-                }
+            for (int o = 0; o < NO; ++o) {
+                if (!valid) a[o] = zero;
+                #pragma unroll
+                for (int i = 0; i < NF; ++i) acc[o][i] = mfma(a[o], b[i], acc[o][i]);
             }
         }
+    }
+    // A lane holds 4 consecutive output channels of each position: stored as
+    // one 8-byte (BF16) or 16-byte (FP32) access when the slice allows it.
+    const bool vy = y.p && ((y.ctot | y.coff) & 3) == 0;
+    const bool v32 = y32.p && ((y32.ctot | y32.coff) & 3) == 0;
+    #pragma unroll
+    for (int o = 0; o < NO; ++o) {
+        const int oc0 = co0 + 16 * o + (grp << 2);
+        const int nbias = max(y.p ? y.c : 0, y32.p ? y32.c : 0);
+        float bo[4];
+        #pragma unroll
+        for (int j = 0; j < 4; ++j) bo[j] = bias && oc0 + j < nbias ? bias[oc0 + j] : 0.f;
+        const bool fy = vy && oc0 + 3 < y.c, f32 = v32 && oc0 + 3 < y32.c;
+        #pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int zl = wave * ZW + i / 4, yl = i % 4;
+            const int64_t pb = (((int64_t)n * x.d + Z0 + zl) * x.h + Y0 + yl) * x.w + X0 + col;
+            f32x4 v;
+            #pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = relu ? fmaxf(acc[o][i][j] + bo[j], 0.f) : acc[o][i][j] + bo[j];
+            if (fy) {
+                const bf16x4 q = {(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+                *reinterpret_cast<bf16x4 *>(reinterpret_cast<bf16 *>(y.p) + pb * y.ctot + y.coff + oc0) = q;
+            } else if (y.p) {
+                #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (oc0 + j < y.c) reinterpret_cast<bf16 *>(y.p)[pb * y.ctot + y.coff + oc0 + j] = (bf16)v[j];
+            }
+            if (f32) {
+                f32x4 *out = reinterpret_cast<f32x4 *>(reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc0);
+                *out = accumulate ? *out + v : v;
+            } else if (y32.p) {
+                #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (oc0 + j < y32.c) {
+                        float *out = reinterpret_cast<float *>(y32.p) + pb * y32.ctot + y32.coff + oc0 + j;
+                        *out = accumulate ? *out + v[j] : v[j];
+                    }
+            }
+        }
+    }
 }
 
 template <int NO, int ZW, int CT>
