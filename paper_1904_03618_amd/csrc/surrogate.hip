@@ -176,6 +176,16 @@ __global__ __launch_bounds__(256) void k_conv_fwd(sg_view x, const bf16 *__restr
 constexpr int BX = 16, BY = 4;
 constexpr int HX = BX + 2, HY = BY + 2;
 
+// Workgroups are dealt to the 8 XCDs in turn by their linear id (x
+// fastest).  This bijection on 0 .. n-1 maps the linear id to a position in
+// the work order such that each XCD gets a contiguous run of it, so that
+// neighbouring bricks, whose halos overlap, share an L2.
+__device__ inline unsigned xcd_contiguous(unsigned lin, unsigned n)
+{
+    const unsigned x = lin & 7u, l = lin >> 3, q = n >> 3, r = n & 7u;
+    return x * q + min(x, r) + l;
+}
+
 template <int NO, int ZW, int CT>
 __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__restrict__ W,
                                                      const float *__restrict__ bias, int pmask, int relu, sg_view y,
@@ -188,7 +198,10 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, grp = lane >> 4;
     const int nbx = x.w / BX, nby = x.h / BY, nbz = x.d / BZ;
-    int bi = blockIdx.x;
+    // work order: output-channel blocks of a brick adjacent, then bricks x-fastest
+    const unsigned ncb = gridDim.y;
+    const unsigned v = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * ncb);
+    int bi = (int)(v / ncb);
     const int bxi = bi % nbx;
     bi /= nbx;
     const int byi = bi % nby;
@@ -196,7 +209,7 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
     const int bzi = bi % nbz;
     const int n = bi / nbz;
     const int X0 = bxi * BX, Y0 = byi * BY, Z0 = bzi * BZ;
-    const int co0 = blockIdx.y * 16 * NO;
+    const int co0 = (int)(v % ncb) * 16 * NO;
     const int ci = x.c, K = 27 * ci;
     const bf16 *xp = reinterpret_cast<const bf16 *>(x.p) + x.coff;
     const bf16 *wrow = W + (int64_t)(co0 + col) * K;
@@ -251,7 +264,7 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
         // K blocks of 4 (tap, 8-channel group) pairs.  The full blocks run
         // unmasked; a last partial block (27 gpt not a multiple of 4) zeroes
         // the weights of its idle lanes.
-        const int G = 27 * gpt, nfull = G >> 2, rem = G & 3, lg = gpt == 1 ? 0 : (gpt == 2 ? 1 : 2);
+        const int G = 27 * gpt, nfull = G >> 2, rem = G & 3, lg = lgp;
         auto fetch = [&](int g, bf16x8 (&a)[NO], bf16x8 (&b)[NF]) {
             const int tap = g >> lg, c8 = g & (gpt - 1);
             const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;

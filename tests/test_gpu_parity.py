@@ -209,6 +209,30 @@ def test_batched_cases_match_single_runs_and_oracle():
         assert_parity(f"batch20_{c}", batch20[c], oracle_run(p, fl, 20), p)
 
 
+def test_batch_with_a_moving_wall_case():
+    """One case with moving walls makes the handle run every case through the
+    moving-wall instantiation of the step kernels.  The moving case equals its
+    single run bit for bit; the cases at rest take the same arithmetic, which
+    the compiler may contract differently in that instantiation, so they equal
+    their runs in a handle without moving walls to FP32 rounding (1e-6
+    relative after 200 steps), and every case matches the oracle."""
+    moving = _moving(W.random_state_case(10, 9, 12, seed=41, bc=(0, 0, 1), theta=(80.0, 100.0)),
+                     ((0.02, 0.0, 0.0), (0.0, -0.015, 0.0)))
+    rest = [W.random_state_case(11, 8, 9, seed=42, bc=(0, 0, 1), theta=(70.0, 130.0)),
+            W.random_state_case(9, 10, 7, seed=43)]
+    cases = [moving] + rest
+    batch = gpu_run(cases, 200)
+    for c, (p, fl) in enumerate(cases):
+        alone = gpu_run([(p, fl)], 200)[0]
+        for k in ("rhoR", "rhoB", "ux", "uy", "uz"):
+            if c == 0:
+                assert np.array_equal(batch[c][k], alone[k]), (c, k)
+            else:
+                scale = max(p["rho_in"]) if k.startswith("rho") else 0.1
+                assert np.abs(batch[c][k] - alone[k]).max() <= 1e-6 * scale, (c, k)
+        assert_parity(f"batch_moving_{c}", batch[c], oracle_run(p, fl, 200), p)
+
+
 def test_batched_uneven_cases_500_steps():
     """Well-conditioned uneven boxes (different sizes, walls, fluids, forcing)
     in one handle against the oracle after 500 steps."""
