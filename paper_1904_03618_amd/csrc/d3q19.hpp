@@ -63,15 +63,11 @@ template <> struct Storage<LBCG_BF16S> {
     __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };
 
-// Population streams are touched once per pass: non-temporal accesses keep
-// them from displacing the reused per-node arrays (aux stencil, stored
-// densities) from L2.
-#ifndef LBCG_NT_LOAD
-#define LBCG_NT_LOAD 1
-#endif
-#ifndef LBCG_NT_STORE
-#define LBCG_NT_STORE 1
-#endif
+// Cache policy of the population streams: loads are non-temporal, so that a
+// pass's stream does not displace the reused per-node arrays (aux stencil,
+// stored densities) from L2; stores are ordinary, so that the level just
+// written is still in the caches when the next pass reads it (measured: FP16S
+// step 152 -> 142 us, FP32 228 -> 221 us on the 128^3 benchmark).
 
 // Buffer-resource access.  A resource (base, size in bytes) is uniform over
 // the wavefront and lives in scalar registers; each lane supplies only a
@@ -120,25 +116,6 @@ __device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, T val
     }
 }
 
-template <class T>
-__device__ inline T ld_stream(const T *p)
-{
-#if LBCG_NT_LOAD
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-
-template <class T>
-__device__ inline void st_stream(T *p, T v)
-{
-#if LBCG_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
-}
 
 // Per-case constants, derived on the host in FP64 and rounded once to FP32.
 struct DevCase {

@@ -553,8 +553,8 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
         const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
         const float db = fs[i] - dr;
         const uint32_t off = (uint32_t)node * (uint32_t)sizeof(P);
-        buf_st<P, CP_STREAM>(rsrc(outb + (size_t)i * NS, NS * sizeof(P)), off,
-                             P{S::enc(dr, a.scale), S::enc(db, a.scale)});
+        buf_st<P, CP_DEFAULT>(rsrc(outb + (size_t)i * NS, NS * sizeof(P)), off,
+                              P{S::enc(dr, a.scale), S::enc(db, a.scale)});
     }
     buf_st<float2, CP_DEFAULT>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u,
                                make_float2(RR, RB));
