@@ -1,0 +1,30 @@
+"""The committed profile summaries describe the current kernels: the HBM
+traffic figures that the benchmark reports were taken on the same step-kernel
+source (a source hash recorded with them), and every summary names the
+command that produced it."""
+import glob
+import json
+import os
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_traffic_profiles_match_the_kernel_source():
+    h = bench.kernel_source_hash()
+    for storage in ("fp32", "fp16s"):
+        path = os.path.join(ROOT, "profiles", f"k_collide_{storage}_galilean128_traffic.json")
+        with open(path) as fh:
+            d = json.load(fh)
+        assert d["kernel_source_sha256_16"] == h, f"{path} was taken on other kernels; profile again"
+        assert abs(d["bytes_per_launch"] - d["bytes_per_node"] * d["nodes"]) < 1.0
+        assert 0.95 < d["bytes_per_node"] / d["algorithmic_bytes_per_node"] < 1.2
+        assert all(c.startswith("rocprofv3 --pmc ") for c in d["commands"])
+
+
+def test_every_summary_names_its_command():
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.txt")):
+        with open(path) as fh:
+            text = fh.read()
+        assert "rocprofv3 " in text, path
