@@ -620,42 +620,60 @@ __global__ void k_up2_fwd(sg_view x, sg_view y)
 }
 
 // 8-channel (16-byte) forms of the two sampling layers for channel-aligned views.
+// One thread per coarse position and 8-channel group: the coarse chunk is read
+// once and written to the 8 fine positions it covers.  Indices are 32-bit
+// (the host checks that the coarse element count fits).
 __global__ void k_up2_fwd8(sg_view x, sg_view y)
 {
-    const int g8 = y.c >> 3;
-    const int64_t n = npos(y) * g8;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = e / g8;
-        const int c = (int)(e - p * g8) << 3;
-        const Pos q = decode(y, p);
-        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + p * y.ctot + y.coff + c) =
-            *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const bf16 *>(x.p) +
-                                              flat(x, q.n, q.z >> 1, q.y >> 1, q.x >> 1) * x.ctot + x.coff + c);
+    const unsigned g8 = (unsigned)y.c >> 3;
+    const unsigned n = (unsigned)npos(x) * g8;
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const unsigned p = e / g8, c = (e - p * g8) << 3;
+        const unsigned px = p % (unsigned)x.w, t1 = p / (unsigned)x.w;
+        const unsigned py = t1 % (unsigned)x.h, t2 = t1 / (unsigned)x.h;
+        const unsigned pz = t2 % (unsigned)x.d, nb = t2 / (unsigned)x.d;
+        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const bf16 *>(x.p) +
+                                                           (int64_t)p * x.ctot + x.coff + c);
+        bf16 *yb = reinterpret_cast<bf16 *>(y.p) + y.coff + c;
+        #pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+            #pragma unroll
+            for (int dy = 0; dy < 2; ++dy) {
+                const int64_t row = (((int64_t)nb * y.d + 2 * pz + dz) * y.h + 2 * py + dy) * y.w + 2 * px;
+                *reinterpret_cast<bf16x8 *>(yb + row * y.ctot) = v;
+                *reinterpret_cast<bf16x8 *>(yb + (row + 1) * y.ctot) = v;
+            }
     }
 }
 
+// One thread per coarse position and 8-channel group; 32-bit indices (the
+// host checks that the coarse element count fits).
 __global__ void k_pool2_fwd8(sg_view x, sg_view y)
 {
-    const int g8 = y.c >> 3;
-    const int64_t n = npos(y) * g8;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = e / g8;
-        const int c = (int)(e - p * g8) << 3;
-        const Pos q = decode(y, p);
+    const unsigned g8 = (unsigned)y.c >> 3;
+    const unsigned n = (unsigned)npos(y) * g8;
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const unsigned p = e / g8, c = (e - p * g8) << 3;
+        const unsigned px = p % (unsigned)y.w, t1 = p / (unsigned)y.w;
+        const unsigned py = t1 % (unsigned)y.h, t2 = t1 / (unsigned)y.h;
+        const unsigned pz = t2 % (unsigned)y.d, nb = t2 / (unsigned)y.d;
         float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        #pragma unroll
         for (int dz = 0; dz < 2; ++dz)
+            #pragma unroll
             for (int dy = 0; dy < 2; ++dy)
+                #pragma unroll
                 for (int dx = 0; dx < 2; ++dx) {
-                    const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
-                        reinterpret_cast<const bf16 *>(x.p) + flat(x, q.n, 2 * q.z + dz, 2 * q.y + dy, 2 * q.x + dx) * x.ctot +
-                        x.coff + c);
+                    const int64_t q = (((int64_t)nb * x.d + 2 * pz + dz) * x.h + 2 * py + dy) * x.w + 2 * px + dx;
+                    const bf16x8 v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const bf16 *>(x.p) +
+                                                                       q * x.ctot + x.coff + c);
                     #pragma unroll
                     for (int j = 0; j < 8; ++j) s[j] += (float)v[j];
                 }
         bf16x8 o;
         #pragma unroll
         for (int j = 0; j < 8; ++j) o[j] = (bf16)(0.125f * s[j]);
-        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + p * y.ctot + y.coff + c) = o;
+        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + (int64_t)p * y.ctot + y.coff + c) = o;
     }
 }
 
@@ -943,7 +961,7 @@ int sg_pool2_fwd(const sg_view *x, const sg_view *y, void *hip_stream)
 {
     if (!ok_view(x) || !ok_view(y) || !half_of(x, y)) return SG_EINVAL;
     const int64_t n = (int64_t)y->n * y->d * y->h * y->w * y->c;
-    if (mfma_view(x) && mfma_view(y))
+    if (mfma_view(x) && mfma_view(y) && n / 8 < (int64_t)1 << 31)
         hipLaunchKernelGGL(k_pool2_fwd8, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
     else
         hipLaunchKernelGGL(k_pool2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
@@ -962,8 +980,8 @@ int sg_up2_fwd(const sg_view *x, const sg_view *y, void *hip_stream)
 {
     if (!ok_view(x) || !ok_view(y) || !half_of(y, x)) return SG_EINVAL;
     const int64_t n = (int64_t)y->n * y->d * y->h * y->w * y->c;
-    if (mfma_view(x) && mfma_view(y))
-        hipLaunchKernelGGL(k_up2_fwd8, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
+    if (mfma_view(x) && mfma_view(y) && n / 64 < (int64_t)1 << 31)
+        hipLaunchKernelGGL(k_up2_fwd8, dim3(grid_for(n / 64)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
     else
         hipLaunchKernelGGL(k_up2_fwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *y);
     return status();
