@@ -464,37 +464,48 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k
     #pragma unroll
     for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
 
+    constexpr int XT = 14;                                 // taps per thread: 27 taps over two parities
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += groups) {
         const int64_t pbase = ch * BPC;
-        __syncthreads();                                   // previous chunk's MFMA reads are done
+        // every load of this thread for the chunk is issued before the barrier
+        // and the LDS stores, so a chunk costs one memory latency
+        bf16x8 xv[XT], dv = zero;
         {
             const int64_t p = pbase + xpos;
             const bool pv = p < P;
             const Pos q = decode(x, pv ? p : 0);
-            for (int t = xtap0; t < taps; t += 2) {
-                bf16x8 v = zero;
-                if (pv && xcv) {
+            #pragma unroll
+            for (int i = 0; i < XT; ++i) {
+                const int t = xtap0 + 2 * i;
+                xv[i] = zero;
+                if (t < taps && pv && xcv) {
                     int dz, dyo, dx;
                     tap_offset(t, k, dz, dyo, dx);
                     const int64_t src = shifted(x, q, dz, dyo, dx, pmask);
-                    if (src >= 0) v = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + c0 + 8 * xc8);
+                    if (src >= 0) xv[i] = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + c0 + 8 * xc8);
                 }
-                #pragma unroll
-                for (int j = 0; j < 8; ++j) xs[t][8 * xc8 + j][xpos] = v[j];
             }
         }
         if (dpos < BPC) {
             const int64_t p = pbase + dpos;
-            bf16x8 v = zero;
             if (p < P && doc < dy.c) {
-                v = *reinterpret_cast<const bf16x8 *>(dp + p * dy.ctot + dy.coff + doc);
+                dv = *reinterpret_cast<const bf16x8 *>(dp + p * dy.ctot + dy.coff + doc);
                 #pragma unroll
                 for (int j = 0; j < 8; ++j)
-                    if (doc + j >= dy.c) v[j] = (bf16)0.f;
+                    if (doc + j >= dy.c) dv[j] = (bf16)0.f;
             }
-            #pragma unroll
-            for (int j = 0; j < 8; ++j) dyt[8 * dc8 + j][dpos] = v[j];
         }
+        __syncthreads();                                   // previous chunk's MFMA reads are done
+        #pragma unroll
+        for (int i = 0; i < XT; ++i) {
+            const int t = xtap0 + 2 * i;
+            if (t < taps)
+                #pragma unroll
+                for (int j = 0; j < 8; ++j) xs[t][8 * xc8 + j][xpos] = xv[i][j];
+        }
+        if (dpos < BPC)
+            #pragma unroll
+            for (int j = 0; j < 8; ++j) dyt[8 * dc8 + j][dpos] = dv[j];
         __syncthreads();
         #pragma unroll
         for (int ks = 0; ks < BPC / 32; ++ks) {
