@@ -15,6 +15,7 @@ namespace sg {
 typedef __bf16 bf16;
 typedef bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // One MFMA 16x16x32 step.  Lane l (0..63) supplies A[l % 16][8 (l / 16) + j]
@@ -444,8 +445,10 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k
     const bf16 *xp = reinterpret_cast<const bf16 *>(x.p);
     const bf16 *dp = reinterpret_cast<const bf16 *>(dy.p);
     const bf16x8 zero = {};
-    // staging roles: x rows: position tid/2 (of 128 lanes per tap parity), 8-channel half tid&1
-    const int xpos = (tid & 127) >> 1, xc8 = tid & 1, xtap0 = tid >> 7;
+    // staging roles: x rows: positions 2m, 2m+1 with m = (tid & 63) / 2, 8-channel
+    // half tid & 1, taps congruent to tid / 64 modulo 4; the two positions of a
+    // channel go to LDS as one 32-bit store
+    const int xpair = (tid & 63) >> 1, xc8 = tid & 1, xtap0 = tid >> 6;
     const bool xcv = c0 + 8 * xc8 < ci;
     // dy rows: position tid / (2 NOB), 8-channel group tid % (2 NOB)
     const int dpos = tid / (2 * NOB), dc8 = tid % (2 * NOB);
@@ -464,25 +467,27 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k
     #pragma unroll
     for (int j = 0; j < 8; ++j) ones[j] = (bf16)1.f;
 
-    constexpr int XT = 14;                                 // taps per thread: 27 taps over two parities
+    constexpr int XT = 7;                                  // taps per thread: 27 taps over four residues
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += groups) {
         const int64_t pbase = ch * BPC;
         // every load of this thread for the chunk is issued before the barrier
         // and the LDS stores, so a chunk costs one memory latency
-        bf16x8 xv[XT], dv = zero;
-        {
-            const int64_t p = pbase + xpos;
+        bf16x8 xv[XT][2], dv = zero;
+        #pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t p = pbase + 2 * xpair + h;
             const bool pv = p < P;
             const Pos q = decode(x, pv ? p : 0);
             #pragma unroll
             for (int i = 0; i < XT; ++i) {
-                const int t = xtap0 + 2 * i;
-                xv[i] = zero;
+                const int t = xtap0 + 4 * i;
+                xv[i][h] = zero;
                 if (t < taps && pv && xcv) {
                     int dz, dyo, dx;
                     tap_offset(t, k, dz, dyo, dx);
                     const int64_t src = shifted(x, q, dz, dyo, dx, pmask);
-                    if (src >= 0) xv[i] = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + c0 + 8 * xc8);
+                    if (src >= 0)
+                        xv[i][h] = *reinterpret_cast<const bf16x8 *>(xp + src * x.ctot + x.coff + c0 + 8 * xc8);
                 }
             }
         }
@@ -498,10 +503,13 @@ __global__ __launch_bounds__(256) void k_conv_bwd_w(sg_view x, sg_view dy, int k
         __syncthreads();                                   // previous chunk's MFMA reads are done
         #pragma unroll
         for (int i = 0; i < XT; ++i) {
-            const int t = xtap0 + 2 * i;
+            const int t = xtap0 + 4 * i;
             if (t < taps)
                 #pragma unroll
-                for (int j = 0; j < 8; ++j) xs[t][8 * xc8 + j][xpos] = xv[i][j];
+                for (int j = 0; j < 8; ++j) {
+                    const bf16x2 pr = {xv[i][0][j], xv[i][1][j]};
+                    *reinterpret_cast<bf16x2 *>(&xs[t][8 * xc8 + j][2 * xpair]) = pr;
+                }
         }
         if (dpos < BPC)
             #pragma unroll
