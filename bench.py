@@ -66,11 +66,13 @@ def dominant(kt, storage):
     return "k_collide", kt["collide"][0] / kt["collide"][1], COLLIDE_BYTES[storage]
 
 
-def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto", kernel_steps=200):
+def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto", kernel_steps=200, repeats=0,
+             repeat_steps=200):
     """Time `steps` steps (no per-kernel events inside the timed region), then,
     if timing, `kernel_steps` more steps with HIP event pairs around every
     kernel for the per-kernel averages.  Fields are taken after the timed
-    steps."""
+    steps.  With repeats > 0, also time that many further runs of
+    repeat_steps steps each (ms per step of each run, returned as kt["repeats"])."""
     import torch
     s = B.Solver(cases, storage=storage, kernel=kernel)
     try:
@@ -84,12 +86,20 @@ def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto", kerne
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         fl = {k: v.double() for k, v in s.fields(0).items() if k != "diag"}
+        reps = []
+        for _ in range(repeats):
+            e0.record()
+            s.step(repeat_steps)
+            e1.record()
+            torch.cuda.synchronize()
+            reps.append(e0.elapsed_time(e1) / repeat_steps)
         kt = None
         if timing:
             B.lbcg_timing(s.h, 1)
             B.lbcg_timing_read(s.h)
             s.step(kernel_steps)
             kt = B.lbcg_timing_read(s.h)
+            kt["repeats"] = reps
         return ms, kt, fl
     finally:
         s.close()
@@ -163,9 +173,33 @@ def cpu_baseline(p, fl, budget_s):
     t = time.time()
     O.run(p, f, n)
     dt = time.time() - t
-    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
-            "sample": f"galilean droplet 128^3, FP64 oracle, {n} timed steps after 1 untimed "
-                      f"({dt:.1f} s)"}
+    out = {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+           "sample": f"galilean droplet 128^3, FP64 oracle, {n} timed steps after 1 untimed "
+                     f"({dt:.1f} s)"}
+    out["one_core"] = cpu_one_core()
+    return out
+
+
+def cpu_one_core():
+    """The same oracle on one core (one step of the full lattice), in a child
+    process started with OMP_NUM_THREADS=1 (the thread count is fixed when
+    OpenMP starts); the child never touches the GPU."""
+    import subprocess
+    code = ("import json, sys, time\n"
+            f"sys.path.insert(0, {ROOT!r})\n"
+            "from oracle import oracle as O\n"
+            "from paper_1904_03618_amd import workloads as W\n"
+            "p, fl = W.galilean_droplet(128, 20.0, seed=1904)\n"
+            "f = O.init(p, fl['rhoR'], fl['rhoB'], fl['ux'], fl['uy'], fl['uz'])\n"
+            "t = time.time(); O.run(p, f, 1); dt = time.time() - t\n"
+            "print(json.dumps({'value': 128 ** 3 / dt / 1e6, 'unit': 'MLUPS', 'cores': O.threads(),\n"
+            "                  'sample': f'one step of the full lattice ({dt:.1f} s)'}))\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
+        return json.loads(r.stdout.strip().splitlines()[-1])
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        return {"error": str(e)[:200]}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -237,7 +271,8 @@ def main():
     N = p["nx"] * p["ny"] * p["nz"]
     cases = [(p, fl)]
 
-    ms, kt, ref = run_form(B, cases, "fp32", args.steps, args.warmup, kernel=args.kernel)
+    ms, kt, ref = run_form(B, cases, "fp32", args.steps, args.warmup, kernel=args.kernel, repeats=5)
+    reps = kt.pop("repeats")
     ms_step = ms / args.steps
     mlups = N * args.steps / (ms * 1e-3) / 1e6
     kname, avg_col, kbytes = dominant(kt, "fp32")
@@ -268,6 +303,8 @@ def main():
                    "lattice": [128, 128, 128], "storage": "fp32", "tau_v": p["tau_v"][0],
                    "parallelism": "single GPU"},
         "step_algorithmic_GBps": mlups * 1e6 * STEP_BYTES["fp32"] / 1e9,
+        "repeat_runs": {"runs": len(reps), "steps": 200, "ms_per_step": reps,
+                        "median_MLUPS": N / (float(np.median(reps)) * 1e-3) / 1e6},
         "kernels_avg_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]},
         "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": ach / HBM_PEAK_GBPS, "kernel": kname + "<fp32>",
