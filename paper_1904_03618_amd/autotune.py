@@ -16,14 +16,22 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.environ.get("LBCG_AUTOTUNE_CACHE", os.path.join(PKG, "autotune_cache.json"))
 
 
+def _moving(p):
+    return any(v != 0.0 for side in p.get("wall_u", ()) for v in side)
+
+
 def box_class(cases, storage):
-    """Cache key: storage, number of cases, wall/periodic mix and the node
-    count rounded to two significant digits."""
+    """Cache key: storage, number of cases, wall/periodic mix, the node count
+    rounded to two significant digits, and the number of cases with moving
+    walls when there are any (those run another instantiation of the step
+    kernels)."""
     n = sum(int(p["nx"]) * int(p["ny"]) * int(p["nz"]) for p, _ in cases)
     walls = sum(1 for p, _ in cases if any(p["bc"]))
     lo = min(min(p["nx"], p["ny"], p["nz"]) for p, _ in cases)
     hi = max(max(p["nx"], p["ny"], p["nz"]) for p, _ in cases)
-    return f"{storage}|cases={len(cases)}|walls={walls}|side={lo}-{hi}|nodes={float(f'{n:.2g}'):.3g}"
+    key = f"{storage}|cases={len(cases)}|walls={walls}|side={lo}-{hi}|nodes={float(f'{n:.2g}'):.3g}"
+    moving = sum(1 for p, _ in cases if _moving(p))
+    return key + (f"|moving={moving}" if moving else "")
 
 
 def candidates(eligible_fused):
@@ -40,8 +48,9 @@ def candidates(eligible_fused):
 
 
 def _fused_ok(cases):
+    """The fused kernel takes walls only on z, neutral (90 deg) and at rest."""
     for p, _ in cases:
-        if p["bc"][0] or p["bc"][1]:
+        if p["bc"][0] or p["bc"][1] or _moving(p):
             return False
         if p["bc"][2] and any(abs(t - 90.0) > 0 for t in p["theta_deg"]):
             return False
