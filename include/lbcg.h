@@ -69,8 +69,12 @@ extern "C" {
  *   wall_u    velocity of the low and high wall of the wall axis (moving
  *             plates, Sec. IV.A); tangential only (the component along the
  *             wall axis must be 0) and zero when no axis is a wall.  A
- *             population reflected at a moving wall gains 2 w_i rho_k
- *             (e_i . U_w) / c_s^2 (c_s^2 = 1/3), rho_k the node's colour density.
+ *             population reflected at a moving wall gains
+ *             f_i^{k,eq}(rho_k, U_w) - f_opp(i)^{k,eq}(rho_k, U_w), twice the
+ *             odd part of the case's equilibrium (Eq. 18, or Eq. 6 when
+ *             improved = 0) at the wall velocity, rho_k the node's colour
+ *             density; a uniform flow at U_w is then left unchanged.  Non-finite
+ *             or non-tangential velocities give LBCG_EINVAL.
  */
 typedef struct lbcg_case {
     int32_t nx, ny, nz;
