@@ -246,6 +246,14 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     steps = steps if steps is not None else int(4.5 * math.sqrt(L / 2e-5)) // every * every
     t_start = t_start if t_start is not None else 5 * every
     assert every % rec == 0
+    # the training trajectories stay on the device: (steps/rec + 1) snapshots of
+    # 4 FP32 fields per amplitude; refuse a recording interval that cannot fit
+    p0, _ = case(L, train_amps[0])
+    need = len(train_amps) * (steps // rec + 1) * 4 * 4 * p0["nx"] * p0["ny"] * p0["nz"]
+    free, _total = torch.cuda.mem_get_info()
+    if need > 0.6 * free:
+        raise ValueError(f"training trajectories need {need / 2**30:.0f} GiB of the {free / 2**30:.0f} GiB free; "
+                         f"record less often (rec > {rec}) or use fewer amplitudes")
     trajs = []
     gen = 0.0
     for a in train_amps:
