@@ -70,6 +70,9 @@ struct Coord {
     bool lo[3], hi[3];           // first / last layer of the wall axis
 };
 
+// WL: the case may have a wall.  Without one (a compile-time false) the wall
+// flags are constants and the bounce-back and ghost-layer code folds away.
+template <bool WL = true>
 __device__ inline Coord make_coord(DC &C, int node)
 {
     Coord c;
@@ -88,9 +91,9 @@ __device__ inline Coord make_coord(DC &C, int node)
     c.o[2][0] = c.z == 0 ? C.N - nxy : -nxy;
     c.o[2][1] = 0;
     c.o[2][2] = c.z == C.nz - 1 ? nxy - C.N : nxy;
-    c.lo[0] = C.wall == 0 && c.x == 0; c.hi[0] = C.wall == 0 && c.x == C.nx - 1;
-    c.lo[1] = C.wall == 1 && c.y == 0; c.hi[1] = C.wall == 1 && c.y == C.ny - 1;
-    c.lo[2] = C.wall == 2 && c.z == 0; c.hi[2] = C.wall == 2 && c.z == C.nz - 1;
+    c.lo[0] = WL && C.wall == 0 && c.x == 0; c.hi[0] = WL && C.wall == 0 && c.x == C.nx - 1;
+    c.lo[1] = WL && C.wall == 1 && c.y == 0; c.hi[1] = WL && C.wall == 1 && c.y == C.ny - 1;
+    c.lo[2] = WL && C.wall == 2 && c.z == 0; c.hi[2] = WL && C.wall == 2 && c.z == C.nz - 1;
     return c;
 }
 
@@ -248,7 +251,7 @@ __device__ inline float phase_field(DC &C, float rR, float rB)
 }
 
 // ----------------------------------------------------------------- k_aux
-template <int ST, bool MV>
+template <int ST, bool MV, bool WL>
 __global__ __launch_bounds__(256) void k_aux(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
@@ -257,7 +260,7 @@ __global__ __launch_bounds__(256) void k_aux(StepArgs a)
         DC &C = case_at(a.cases, tl.x);
         const int node = tl.y + (int)threadIdx.x;
         if (node >= C.N) continue;
-        const Coord c = make_coord(C, node);
+        const Coord c = make_coord<WL>(C, node);
         NodeState s;
         pull_node<ST, MV>(a, C, c, s);
         const Macro m = macro(C, s);
@@ -561,7 +564,7 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
 }
 
 // ------------------------------------------------------------- k_collide
-template <int ST, bool MV>
+template <int ST, bool MV, bool WL>
 __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
@@ -570,7 +573,7 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
         DC &C = case_at(a.cases, tl.x);
         const int node = tl.y + (int)threadIdx.x;
         if (node >= C.N) continue;
-        const Coord c = make_coord(C, node);
+        const Coord c = make_coord<WL>(C, node);
         NodeState s;
         pull_node<ST, MV>(a, C, c, s);
         Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};

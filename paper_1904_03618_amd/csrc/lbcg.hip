@@ -236,9 +236,11 @@ int launch_step(lbcg_handle *h, hipStream_t st)
         return LBCG_OK;
     }
     const int grid = h->persistent > 0 ? h->persistent : h->ntiles;
+    // instantiation by what the handle's cases need: moving walls, walls, neither
     int rc = timed(h, 0, [&] {
-        if (h->moving) hipLaunchKernelGGL((k_aux<ST, true>), dim3(grid), dim3(h->block), 0, st, a);
-        else hipLaunchKernelGGL((k_aux<ST, false>), dim3(grid), dim3(h->block), 0, st, a);
+        if (h->moving) hipLaunchKernelGGL((k_aux<ST, true, true>), dim3(grid), dim3(h->block), 0, st, a);
+        else if (h->has_wall) hipLaunchKernelGGL((k_aux<ST, false, true>), dim3(grid), dim3(h->block), 0, st, a);
+        else hipLaunchKernelGGL((k_aux<ST, false, false>), dim3(grid), dim3(h->block), 0, st, a);
     });
     if (!rc && h->has_wall)
         rc = timed(h, 1, [&] {
@@ -247,8 +249,10 @@ int launch_step(lbcg_handle *h, hipStream_t st)
         });
     if (!rc)
         rc = timed(h, 2, [&] {
-            if (h->moving) hipLaunchKernelGGL((k_collide<ST, true>), dim3(grid), dim3(h->block), 0, st, a);
-            else hipLaunchKernelGGL((k_collide<ST, false>), dim3(grid), dim3(h->block), 0, st, a);
+            if (h->moving) hipLaunchKernelGGL((k_collide<ST, true, true>), dim3(grid), dim3(h->block), 0, st, a);
+            else if (h->has_wall)
+                hipLaunchKernelGGL((k_collide<ST, false, true>), dim3(grid), dim3(h->block), 0, st, a);
+            else hipLaunchKernelGGL((k_collide<ST, false, false>), dim3(grid), dim3(h->block), 0, st, a);
         });
     if (rc) return rc;
     HIPCHK(hipGetLastError());
