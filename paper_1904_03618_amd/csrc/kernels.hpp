@@ -70,9 +70,13 @@ struct Coord {
     bool lo[3], hi[3];           // first / last layer of the wall axis
 };
 
-// WL: the case may have a wall.  Without one (a compile-time false) the wall
-// flags are constants and the bounce-back and ghost-layer code folds away.
-template <bool WL = true>
+// WL: which walls the cases of the launch may have: WALLS_NONE, WALLS_Z (walls
+// only on the z axis, or none) or WALLS_ANY.  With fewer possibilities the
+// wall flags of the other axes are compile-time false and the bounce-back and
+// ghost-layer code for them folds away.
+constexpr int WALLS_NONE = 0, WALLS_Z = 1, WALLS_ANY = 2;
+
+template <int WL = WALLS_ANY>
 __device__ inline Coord make_coord(DC &C, int node)
 {
     Coord c;
@@ -91,9 +95,10 @@ __device__ inline Coord make_coord(DC &C, int node)
     c.o[2][0] = c.z == 0 ? C.N - nxy : -nxy;
     c.o[2][1] = 0;
     c.o[2][2] = c.z == C.nz - 1 ? nxy - C.N : nxy;
-    c.lo[0] = WL && C.wall == 0 && c.x == 0; c.hi[0] = WL && C.wall == 0 && c.x == C.nx - 1;
-    c.lo[1] = WL && C.wall == 1 && c.y == 0; c.hi[1] = WL && C.wall == 1 && c.y == C.ny - 1;
-    c.lo[2] = WL && C.wall == 2 && c.z == 0; c.hi[2] = WL && C.wall == 2 && c.z == C.nz - 1;
+    constexpr bool xy = WL == WALLS_ANY, zz = WL != WALLS_NONE;
+    c.lo[0] = xy && C.wall == 0 && c.x == 0; c.hi[0] = xy && C.wall == 0 && c.x == C.nx - 1;
+    c.lo[1] = xy && C.wall == 1 && c.y == 0; c.hi[1] = xy && C.wall == 1 && c.y == C.ny - 1;
+    c.lo[2] = zz && C.wall == 2 && c.z == 0; c.hi[2] = zz && C.wall == 2 && c.z == C.nz - 1;
     return c;
 }
 
@@ -251,7 +256,7 @@ __device__ inline float phase_field(DC &C, float rR, float rB)
 }
 
 // ----------------------------------------------------------------- k_aux
-template <int ST, bool MV, bool WL>
+template <int ST, bool MV, int WL>
 __global__ __launch_bounds__(256) void k_aux(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);
@@ -564,7 +569,7 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
 }
 
 // ------------------------------------------------------------- k_collide
-template <int ST, bool MV, bool WL>
+template <int ST, bool MV, int WL>
 __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 {
     const TileRange tr = tile_range(a.ntiles);

@@ -57,6 +57,7 @@ struct lbcg_handle {
     float scale = 1.0f, inv_scale = 1.0f;
     bool has_wall = false;
     bool moving = false;               // some case has a moving wall: step kernels with the wall gain
+    int walls = WALLS_NONE;            // which walls the cases have (selects the step-kernel instantiation)
     bool alive = true;
     // kernel timing (lbcg_timing): event pool and pending (kernel, start, end)
     bool timing = false;
@@ -236,11 +237,15 @@ int launch_step(lbcg_handle *h, hipStream_t st)
         return LBCG_OK;
     }
     const int grid = h->persistent > 0 ? h->persistent : h->ntiles;
-    // instantiation by what the handle's cases need: moving walls, walls, neither
+    // instantiation by what the handle's cases need: moving walls, walls on
+    // any axis, walls only on z, no walls
     int rc = timed(h, 0, [&] {
-        if (h->moving) hipLaunchKernelGGL((k_aux<ST, true, true>), dim3(grid), dim3(h->block), 0, st, a);
-        else if (h->has_wall) hipLaunchKernelGGL((k_aux<ST, false, true>), dim3(grid), dim3(h->block), 0, st, a);
-        else hipLaunchKernelGGL((k_aux<ST, false, false>), dim3(grid), dim3(h->block), 0, st, a);
+        if (h->moving) hipLaunchKernelGGL((k_aux<ST, true, WALLS_ANY>), dim3(grid), dim3(h->block), 0, st, a);
+        else if (h->walls == WALLS_ANY)
+            hipLaunchKernelGGL((k_aux<ST, false, WALLS_ANY>), dim3(grid), dim3(h->block), 0, st, a);
+        else if (h->walls == WALLS_Z)
+            hipLaunchKernelGGL((k_aux<ST, false, WALLS_Z>), dim3(grid), dim3(h->block), 0, st, a);
+        else hipLaunchKernelGGL((k_aux<ST, false, WALLS_NONE>), dim3(grid), dim3(h->block), 0, st, a);
     });
     if (!rc && h->has_wall)
         rc = timed(h, 1, [&] {
@@ -249,10 +254,13 @@ int launch_step(lbcg_handle *h, hipStream_t st)
         });
     if (!rc)
         rc = timed(h, 2, [&] {
-            if (h->moving) hipLaunchKernelGGL((k_collide<ST, true, true>), dim3(grid), dim3(h->block), 0, st, a);
-            else if (h->has_wall)
-                hipLaunchKernelGGL((k_collide<ST, false, true>), dim3(grid), dim3(h->block), 0, st, a);
-            else hipLaunchKernelGGL((k_collide<ST, false, false>), dim3(grid), dim3(h->block), 0, st, a);
+            if (h->moving)
+                hipLaunchKernelGGL((k_collide<ST, true, WALLS_ANY>), dim3(grid), dim3(h->block), 0, st, a);
+            else if (h->walls == WALLS_ANY)
+                hipLaunchKernelGGL((k_collide<ST, false, WALLS_ANY>), dim3(grid), dim3(h->block), 0, st, a);
+            else if (h->walls == WALLS_Z)
+                hipLaunchKernelGGL((k_collide<ST, false, WALLS_Z>), dim3(grid), dim3(h->block), 0, st, a);
+            else hipLaunchKernelGGL((k_collide<ST, false, WALLS_NONE>), dim3(grid), dim3(h->block), 0, st, a);
         });
     if (rc) return rc;
     HIPCHK(hipGetLastError());
@@ -478,6 +486,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         h->total_nodes += d.NS;
         h->total_ghost += (int64_t)2 * d.plane;
         if (d.wall >= 0) h->has_wall = true;
+        if (d.wall >= 0) h->walls = std::max(h->walls, d.wall == 2 ? WALLS_Z : WALLS_ANY);
         if (d.moving) h->moving = true;
         h->tile_begin.push_back((int)tiles.size());
         for (int n0 = 0; n0 < d.N; n0 += h->block) tiles.push_back(make_int2(c, n0));
