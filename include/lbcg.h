@@ -140,9 +140,11 @@ typedef struct lbcg_handle lbcg_handle;
  * (Eq. 6) equilibrium at time level 0.  hip_stream is a hipStream_t (may be
  * NULL).  On success *out receives the handle, which owns all device memory
  * it allocates.  Errors: LBCG_EINVAL (n_cases < 1, any dimension < 1, more
- * than one wall axis, alpha outside [0,1), a relaxation time <= 1/2,
- * rho_in <= 0, broken pressure balance, NULL pointer), LBCG_ENOMEM,
- * LBCG_EDEVICE.
+ * than 2^28 - 64 nodes in one case (the kernels use 32-bit byte offsets within
+ * a case; a larger domain is split into cases or GPUs), more than one wall
+ * axis, alpha outside [0,1), a relaxation time <= 1/2, rho_in <= 0, broken
+ * pressure balance, a non-tangential or non-finite wall velocity, NULL
+ * pointer), LBCG_ENOMEM, LBCG_EDEVICE.
  */
 int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init,
               const lbcg_options *opt, void *hip_stream, lbcg_handle **out);

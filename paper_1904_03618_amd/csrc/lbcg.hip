@@ -89,7 +89,11 @@ int validate(const lbcg_case &c, int idx)
         return fail(LBCG_EINVAL, buf);
     };
     if (c.nx < 1 || c.ny < 1 || c.nz < 1) return bad("dimensions must be >= 1");
-    if ((int64_t)c.nx * c.ny * c.nz > (int64_t)1 << 30) return bad("more than 2^30 nodes in one case");
+    // the kernels address a case's arrays through 32-bit byte offsets: a pair of
+    // FP32 population arrays (2 x 8 B per node) and the aux array (16 B per
+    // node) must stay below 4 GiB
+    if ((int64_t)c.nx * c.ny * c.nz > ((int64_t)1 << 28) - 64)
+        return bad("more than 2^28 - 64 nodes in one case (32-bit buffer offsets)");
     int walls = 0;
     for (int a = 0; a < 3; ++a) {
         if (c.bc[a] != LBCG_PERIODIC && c.bc[a] != LBCG_WALL) return bad("bc must be PERIODIC or WALL");

@@ -62,6 +62,8 @@ def _init_rc(p, fl=None, opt=None, n=1):
     (dict(rho_in=(-1.0, 1.0)), "rho_in"),
     (dict(theta_deg=(0.0, 90.0)), "theta"),
     (dict(improved=2), "improved"),
+    (dict(wall_u=((0.01, 0.0, 0.0), (0.0, 0.0, 0.0))), "wall axis"),
+    (dict(bc=(0, 0, 1), wall_u=((0.0, 0.0, 0.01), (0.0, 0.0, 0.0))), "tangential"),
 ])
 def test_init_rejects_invalid_parameters(change, frag):
     p, _ = W.paper_fluids_droplet(4, 1.0)
@@ -100,3 +102,19 @@ def test_calls_on_null_handle_fail_cleanly():
     buf = C.create_string_buffer(64)
     assert L.lbcg_checkpoint_save(None, buf, 64) == B.LBCG_ESTATE
     assert L.lbcg_checkpoint_load(None, buf, 64) == B.LBCG_ESTATE
+
+
+def test_init_rejects_cases_beyond_32_bit_offsets():
+    """A case whose arrays would exceed the kernels' 32-bit byte offsets is
+    rejected before any field is read (the field pointers here are tiny)."""
+    L = B.load()
+    p, _ = W.paper_fluids_droplet(4, 1.0)
+    p = dict(p, nx=1024, ny=1024, nz=256)              # 2^28 nodes
+    tiny = np.zeros(4)
+    cs = (B.lbcg_case * 1)(B.pack_case(p))
+    fs = (B.lbcg_fields * 1)()
+    fs[0].rhoR = fs[0].rhoB = fs[0].ux = fs[0].uy = fs[0].uz = tiny.ctypes.data
+    h = C.c_void_p()
+    o = B.lbcg_options(0, 0, 0, 0, 0, 0, 0, 0)
+    assert L.lbcg_init(cs, 1, fs, C.byref(o), None, C.byref(h)) == B.LBCG_EINVAL
+    assert h.value is None and "2^28" in B.lbcg_last_error()
