@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_set>
 #include <vector>
 
 #include "kernels.hpp"
@@ -416,9 +418,24 @@ int init_any(lbcg_handle *h, int cid, const lbcg_case &c, const lbcg_fields &f)
     }
 }
 
+// Handles returned by lbcg_init and not yet freed.  A freed (or never
+// issued) pointer is recognised without reading it.
+std::mutex g_handles_mu;
+std::unordered_set<const lbcg_handle *> g_handles;
+
+bool live(const lbcg_handle *h)
+{
+    std::lock_guard<std::mutex> lk(g_handles_mu);
+    return h && g_handles.count(h) && h->alive;
+}
+
 int check_handle(const lbcg_handle *h)
 {
-    if (!h || !h->alive) return fail(LBCG_ESTATE, "invalid or freed handle");
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        if (!h || !g_handles.count(h)) return fail(LBCG_ESTATE, "invalid or freed handle");
+    }
+    if (!h->alive) return fail(LBCG_ESTATE, "invalid or freed handle");
     return LBCG_OK;
 }
 
@@ -574,6 +591,10 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         delete h;
         return rc;
     }
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        g_handles.insert(h);
+    }
     *out = h;
     return LBCG_OK;
 }
@@ -658,6 +679,10 @@ int lbcg_free(lbcg_handle *h)
 {
     int rc = check_handle(h);
     if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_handles_mu);
+        g_handles.erase(h);
+    }
     (void)hipStreamSynchronize(h->stream);
     release(h);
     h->alive = false;
@@ -665,15 +690,15 @@ int lbcg_free(lbcg_handle *h)
     return LBCG_OK;
 }
 
-int64_t lbcg_steps_done(const lbcg_handle *h) { return h ? h->steps : -1; }
+int64_t lbcg_steps_done(const lbcg_handle *h) { return live(h) ? h->steps : -1; }
 
 int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id)
 {
-    if (!h || case_id < 0 || case_id >= h->ncases) return -1;
+    if (!live(h) || case_id < 0 || case_id >= h->ncases) return -1;
     return h->dc[case_id].N;
 }
 
-int32_t lbcg_storage_bytes(const lbcg_handle *h) { return h ? h->elem : -1; }
+int32_t lbcg_storage_bytes(const lbcg_handle *h) { return live(h) ? h->elem : -1; }
 
 int lbcg_timing(lbcg_handle *h, int32_t enable)
 {
@@ -737,7 +762,7 @@ int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f)
 
 int64_t lbcg_checkpoint_bytes(const lbcg_handle *h)
 {
-    if (!h || !h->alive) return -1;
+    if (!live(h)) return -1;
     return ckpt_bytes(h);
 }
 

@@ -118,3 +118,14 @@ def test_init_rejects_cases_beyond_32_bit_offsets():
     o = B.lbcg_options(0, 0, 0, 0, 0, 0, 0, 0)
     assert L.lbcg_init(cs, 1, fs, C.byref(o), None, C.byref(h)) == B.LBCG_EINVAL
     assert h.value is None and "2^28" in B.lbcg_last_error()
+
+
+def test_never_issued_handle_is_rejected_without_being_read():
+    """A pointer lbcg_init never returned is recognised from the registry of
+    live handles, so no call dereferences it."""
+    L = B.load()
+    bogus = C.c_void_p(0x1000)
+    assert L.lbcg_step(bogus, 1) == B.LBCG_ESTATE
+    assert L.lbcg_free(bogus) == B.LBCG_ESTATE
+    assert L.lbcg_steps_done(bogus) == -1 and L.lbcg_case_nodes(bogus, 0) == -1
+    assert L.lbcg_storage_bytes(bogus) == -1 and L.lbcg_checkpoint_bytes(bogus) == -1

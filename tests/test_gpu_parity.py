@@ -367,6 +367,21 @@ def test_checkpoint_resume_is_bitwise(storage):
         B.lbcg_free(hb)
 
 
+def test_freed_handle_is_rejected():
+    """After lbcg_free the handle is unusable: a second free, a step and the
+    accessors fail cleanly instead of touching freed memory."""
+    import ctypes as C
+    from paper_1904_03618_amd import lbcg as B
+    L = B.load()
+    p, fl = W.random_state_case(6, 5, 4, seed=1)
+    h = B.lbcg_init([(p, fl)])
+    assert L.lbcg_steps_done(C.c_void_p(h)) == 0
+    assert L.lbcg_free(C.c_void_p(h)) == B.LBCG_OK
+    assert L.lbcg_free(C.c_void_p(h)) == B.LBCG_ESTATE
+    assert L.lbcg_step(C.c_void_p(h), 1) == B.LBCG_ESTATE
+    assert L.lbcg_steps_done(C.c_void_p(h)) == -1
+
+
 def test_tile_shape_does_not_change_result():
     """No atomics in the step: tile size and persistent scheduling give
     bitwise identical populations."""
