@@ -52,6 +52,32 @@ def conv3d(x, W, bias=None, k=3, pmask=0):
     return y
 
 
+def conv3d_at(x, W, points, bias=None, k=3, pmask=0):
+    """The convolution's definition evaluated at selected output positions
+    only (points: (m, 4) integer array of (n, z, y, x)), for layers too large
+    to evaluate whole: y[p, o] = b[o] + sum_t sum_c W[o, t*ci + c] x[p + off(t), c]."""
+    n, d, h, w, ci = x.shape
+    co = W.shape[0]
+    offs = tap_offsets(k)
+    Wr = W.reshape(co, len(offs), ci)
+    out = np.zeros((len(points), co))
+    for j, (b, z, y, xx) in enumerate(np.asarray(points)):
+        acc = np.zeros(co) if bias is None else np.array(bias, dtype=np.float64)
+        for t, (dz, dy, dx) in enumerate(offs):
+            q = [z + dz, y + dy, xx + dx]
+            ok = True
+            for a, (size, bit) in enumerate(((d, 4), (h, 2), (w, 1))):
+                if q[a] < 0 or q[a] >= size:
+                    if pmask & bit:
+                        q[a] %= size
+                    else:
+                        ok = False
+            if ok:
+                acc = acc + Wr[:, t, :] @ x[b, q[0], q[1], q[2], :]
+        out[j] = acc
+    return out
+
+
 def conv3d_bwd_data(dy, W, ci, k=3, pmask=0):
     """dx = adjoint of x -> conv3d(x, W) applied to dy."""
     co = W.shape[0]

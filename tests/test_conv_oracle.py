@@ -91,3 +91,18 @@ def test_adam_first_step():
     w1, m, v = R.adam(w, g, np.zeros(3), np.zeros(3), lr=0.01, b1=0.9, b2=0.999, eps=1e-8, step=1)
     assert np.allclose(w1, w - 0.01 * g / (np.abs(g) + 1e-8))
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+@pytest.mark.parametrize("pmask", [0, 5, 7])
+def test_pointwise_convolution_matches_the_whole_layer(pmask):
+    """conv3d_at (positions one by one, used for layers too large for the
+    whole-layer reference) equals conv3d, including positions on every face."""
+    rng = np.random.default_rng(3 + pmask)
+    x = rng.standard_normal((2, 4, 5, 6, 3))
+    W = rng.standard_normal((4, 27 * 3))
+    b = rng.standard_normal(4)
+    full = R.conv3d(x, W, b, k=3, pmask=pmask)
+    pts = np.array([(0, 0, 0, 0), (1, 3, 4, 5), (0, 2, 0, 5), (1, 0, 4, 0), (1, 2, 2, 3)])
+    got = R.conv3d_at(x, W, pts, b, k=3, pmask=pmask)
+    want = np.array([full[b_, z, y, xx] for b_, z, y, xx in pts])
+    assert np.allclose(got, want, rtol=1e-12, atol=1e-12)
