@@ -860,8 +860,13 @@ int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co
         hipStream_t st = (hipStream_t)hip_stream;
         const sg_view yv = y ? *y : none, y32v = y32 ? *y32 : none;
         const bool deep = x->c % 32 != 0 && x->d % 8 == 0;   // few or odd channel counts: two planes per wave
+        // two planes per wave also for 32-channel chunks when that still leaves
+        // at least 512 workgroups (large layers: less halo per output; measured
+        // on the U-Net, smaller layers lose from the fewer workgroups)
+        const bool big = x->d % 8 == 0 && P / (BX * BY * 8) * (co / 32) >= 512;
         if (co % 32 == 0) {
             if (deep) launch_brick<2, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+            else if (big) launch_brick<2, 2, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
             else launch_brick<2, 1, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
         } else {
             if (deep) launch_brick<1, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);

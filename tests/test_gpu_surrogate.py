@@ -84,6 +84,34 @@ def test_conv_forward_data_and_weight_gradients(k, pmask, shape, ctot, coff, ci,
     assert ok and ok2, (err, err2)
 
 
+@pytest.mark.parametrize("pmask", [3, 0])
+def test_large_layer_two_plane_bricks(pmask):
+    """A layer large enough for the two-plane, 32-channel brick (1 x 64 x 64 x
+    128 positions, 32 -> 64 channels: 2048 workgroups, above the 512 that
+    select it), checked at
+    sampled positions (faces and corners included) against the convolution's
+    definition evaluated there."""
+    import torch
+    from oracle import conv_ref as R
+    from paper_1904_03618_amd import surrogate as S
+    rng = np.random.default_rng(91 + pmask)
+    n, d, h, w, ci, co = 1, 64, 64, 128, 32, 64
+    xt, x64 = bft(rng.standard_normal((n, d, h, w, ci)))
+    layer = S.Conv("big", ci, co, 3, False, rng)
+    layer.b.copy_(torch.tensor(rng.standard_normal(co).astype(np.float32)))
+    layer.prep()
+    W64 = layer.w.to(torch.bfloat16).float().cpu().numpy().astype(np.float64)
+    b64 = layer.b.cpu().numpy().astype(np.float64)
+    y32 = torch.zeros((n, d, h, w, co), device="cuda")
+    layer.fwd(S.view(xt), None, S.view(y32), pmask=pmask)
+    pts = np.stack([rng.integers(0, s_, 300) for s_ in (n, d, h, w)], axis=1)
+    pts = np.concatenate([pts, [(0, 0, 0, 0), (0, d - 1, h - 1, w - 1), (0, 0, h - 1, 0), (0, d - 1, 0, w - 1)]])
+    got = y32.cpu().numpy()[pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3]]
+    ok, err = close(got, R.conv3d_at(x64, W64, pts, b64, k=3, pmask=pmask))
+    print("large layer", pmask, err, flush=True)
+    assert ok, err
+
+
 def test_elementwise_layers():
     import torch
     from oracle import conv_ref as R
