@@ -133,6 +133,45 @@ def test_parity_500_steps(name):
     assert_parity(name, g, o, p)
 
 
+def _degenerate_cases():
+    """Boxes with extents of one and two nodes: the periodic neighbours of a
+    one-node axis are the node itself, those of a two-node axis coincide, and
+    a one-layer wall axis has both walls (and both ghost layers) on the same
+    layer.  Smooth random states with a body force; two of them with moving
+    walls.  The FP64 oracle moves by 2e-8 at most under a 1e-7 relative
+    perturbation of these states over 200 steps, so the standard tolerances
+    apply."""
+    spec = {
+        "line_z_walls_1x1x8": ((1, 1, 8), dict(bc=(0, 0, 1), theta=(60.0, 120.0)), None),
+        "sheet_2x3x1": ((2, 3, 1), dict(bc=(0, 0, 0)), None),
+        "single_layer_walls_4x5x1": ((4, 5, 1), dict(bc=(0, 0, 1), theta=(70.0, 100.0)), None),
+        "thin_y_moving_1x6x5": ((1, 6, 5), dict(bc=(0, 1, 0), theta=(80.0, 130.0)),
+                                ((0.02, 0.0, -0.01), (0.0, 0.0, 0.015))),
+        "two_wide_wall_x_2x2x3": ((2, 2, 3), dict(bc=(1, 0, 0), theta=(100.0, 75.0)),
+                                  ((0.0, 0.01, 0.0), (0.0, 0.0, -0.02))),
+        "needle_x_9x1x1": ((9, 1, 1), dict(bc=(0, 0, 0)), None),
+    }
+    out = {}
+    for name, (dims, kw, wu) in spec.items():
+        p, fl = W.random_state_case(*dims, seed=21, force=(1e-5, 0.0, -2e-5), **kw)
+        out[name] = (dict(p, wall_u=wu) if wu else p, fl)
+    return out
+
+
+@pytest.mark.parametrize("name", list(_degenerate_cases()))
+def test_degenerate_extents_200_steps(name):
+    p, fl = _degenerate_cases()[name]
+    assert_parity(name, gpu_run([(p, fl)], 200)[0], oracle_run(p, fl, 200), p)
+
+
+def test_degenerate_extents_in_one_batch():
+    """The same boxes in one handle (so on the moving-wall instantiation of the
+    step kernels) against the oracle."""
+    cases = list(_degenerate_cases().values())
+    for (p, fl), g in zip(cases, gpu_run(cases, 200)):
+        assert_parity("batch", g, oracle_run(p, fl, 200), p)
+
+
 def test_channel_density_ratio_10():
     """Layered channel, density and viscosity ratio 10 (rho_R^in = 10).  This
     steady, plane-uniform state makes FP32 rounding of the O(10) populations
