@@ -458,6 +458,40 @@ def test_full_size_galilean_128():
     assert np.allclose(g2["diag"][2:], d0[2:], rtol=1e-4)
 
 
+def test_full_size_impact_batch_fp16s():
+    """The 256-box droplet-impact batch (sides 48..128, 2.1e8 nodes) in FP16S
+    with the launch shape the batch benchmark uses (256-node tiles, no
+    persistent grid, 8-step HIP graphs): two of the smallest boxes and the
+    largest, node by node against the oracle after 8 steps at the FP16S
+    bounds, and every box finite with its colour masses kept."""
+    import torch
+    from paper_1904_03618_amd import lbcg as B
+    cases = W.impact_batch(256)
+    sizes = [p["nx"] for p, _ in cases]
+    sample = sorted(range(len(cases)), key=lambda c: (sizes[c], c))[:2] + [int(np.argmax(sizes))]
+    s = B.Solver(cases, storage="fp16s", diag_every=0, kernel="twopass", block_nodes=256,
+                 persistent_blocks=0, graph_steps=8)
+    try:
+        m0 = np.array([B.lbcg_moments(s.h, c) for c in range(len(cases))])
+        s.step(8)
+        m1 = np.array([B.lbcg_moments(s.h, c) for c in range(len(cases))])
+        got = {}
+        for c in sample:
+            fl = s.fields(c)
+            torch.cuda.synchronize()
+            got[c] = {k: (v.double().cpu().numpy() if k != "diag" else v) for k, v in fl.items()}
+    finally:
+        s.close()
+    assert np.isfinite(m1).all()
+    rel = np.abs(m1[:, :2] - m0[:, :2]) / m0[:, :2]
+    print("impact batch: max relative colour-mass change after 8 steps", rel.max(), flush=True)
+    assert rel.max() < 1e-4
+    for c in sample:
+        p, fl = cases[c]
+        assert_parity(f"impact_batch_case{c}_L{sizes[c]}", got[c], oracle_run(p, fl, 8), p, tn=6e-3, tu=2e-4,
+                      tr=6e-3)
+
+
 def test_unstable_state_is_reported():
     """A NaN in the initial velocity (set on the host) makes the periodic
     stability check return LBCG_EUNSTABLE at the first check."""
