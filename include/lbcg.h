@@ -181,7 +181,11 @@ int lbcg_moments(lbcg_handle *h, int32_t case_id, float *rhoR, float *rhoB, floa
  * LBCG_ENOMEM, LBCG_EDEVICE. */
 int lbcg_set_fields(lbcg_handle *h, int32_t case_id, const lbcg_fields *fields);
 
-/* Release every device resource of the handle.  LBCG_ESTATE for NULL. */
+/* Release every device resource of the handle after the stream's pending work
+ * has finished.  LBCG_ESTATE for NULL, for an already freed handle and for a
+ * pointer lbcg_init never returned (the library keeps a registry of live
+ * handles and never reads such a pointer).  Every other call also returns
+ * LBCG_ESTATE (or -1) for such pointers. */
 int lbcg_free(lbcg_handle *h);
 
 /* ---- inspection helpers (tests, checkpoints) ---- */
