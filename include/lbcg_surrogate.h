@@ -73,6 +73,15 @@ int sg_pool2_bwd(const sg_view *dy, const sg_view *dx, int32_t accumulate, void 
 int sg_up2_fwd(const sg_view *x, const sg_view *y, void *hip_stream);
 int sg_up2_bwd(const sg_view *dy, const sg_view *dx, int32_t accumulate, void *hip_stream);
 
+/* Upsampling into a concatenation: y (BF16, fine) receives in its first x->c
+ * channels the nearest 2x upsampling of x (BF16, coarse) and in the next
+ * skip->c channels a copy of skip (BF16, y's positions); y->c must equal
+ * x->c + skip->c.  Adjacent threads write adjacent 16-byte chunks of y's
+ * rows, so a y that interleaves the two parts per position is still written
+ * in whole lines.  Channel counts, strides and offsets multiples of 8; y's
+ * 8-channel chunk count below 2^31.  SG_EINVAL otherwise. */
+int sg_up2_cat_fwd(const sg_view *x, const sg_view *skip, const sg_view *y, void *hip_stream);
+
 /* Mean-squared error of an FP32 view against an FP32 target of the same
  * shape: grad = 2 (out - target) / count into an FP32 view.  loss: device
  * array of 257 doubles; loss[0] receives the mean square, loss[1..256] are

@@ -665,6 +665,32 @@ __global__ void k_up2_fwd8(sg_view x, sg_view y)
     }
 }
 
+// Upsampling into a concatenation: y's first x.c channels are the nearest 2x
+// upsampling of x, the remaining ones a copy of `skip` (same positions as y).
+// One thread per fine position and 8-channel group of y, so that a position's
+// whole row of y is written by adjacent lanes: full-line writes even where y
+// interleaves the two parts per position.  32-bit indices (host-checked).
+__global__ void k_up2_cat8(sg_view x, sg_view skip, sg_view y)
+{
+    const unsigned g8 = (unsigned)y.c >> 3, gx = (unsigned)x.c >> 3;
+    const unsigned n = (unsigned)npos(y) * g8;
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const unsigned p = e / g8, g = e - p * g8;
+        bf16x8 v;
+        if (g < gx) {
+            const unsigned fx = p % (unsigned)y.w, t1 = p / (unsigned)y.w;
+            const unsigned fy = t1 % (unsigned)y.h, t2 = t1 / (unsigned)y.h;
+            const unsigned fz = t2 % (unsigned)y.d, nb = t2 / (unsigned)y.d;
+            const int64_t q = (((int64_t)nb * x.d + (fz >> 1)) * x.h + (fy >> 1)) * x.w + (fx >> 1);
+            v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const bf16 *>(x.p) + q * x.ctot + x.coff + 8 * g);
+        } else {
+            v = *reinterpret_cast<const bf16x8 *>(reinterpret_cast<const bf16 *>(skip.p) + (int64_t)p * skip.ctot +
+                                                  skip.coff + 8 * (g - gx));
+        }
+        *reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(y.p) + (int64_t)p * y.ctot + y.coff + 8 * g) = v;
+    }
+}
+
 // One thread per coarse position and 8-channel group; 32-bit indices (the
 // host checks that the coarse element count fits).
 __global__ void k_pool2_fwd8(sg_view x, sg_view y)
@@ -997,6 +1023,17 @@ int sg_pool2_bwd(const sg_view *dy, const sg_view *dx, int32_t accumulate, void 
     if (!ok_view(dy) || !ok_view(dx) || !half_of(dx, dy)) return SG_EINVAL;
     const int64_t n = (int64_t)dx->n * dx->d * dx->h * dx->w * dx->c;
     hipLaunchKernelGGL(k_pool2_bwd, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *dy, *dx, accumulate);
+    return status();
+}
+
+int sg_up2_cat_fwd(const sg_view *x, const sg_view *skip, const sg_view *y, void *hip_stream)
+{
+    if (!mfma_view(x) || !mfma_view(skip) || !mfma_view(y)) return SG_EINVAL;
+    if (y->n != x->n || y->d != 2 * x->d || y->h != 2 * x->h || y->w != 2 * x->w) return SG_EINVAL;
+    if (!same_pos(y, skip) || y->c != x->c + skip->c) return SG_EINVAL;
+    const int64_t n = (int64_t)y->n * y->d * y->h * y->w * (y->c / 8);
+    if (n >= (int64_t)1 << 31) return SG_EINVAL;
+    hipLaunchKernelGGL(k_up2_cat8, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)hip_stream, *x, *skip, *y);
     return status();
 }
 

@@ -38,7 +38,7 @@ class sg_view(C.Structure):
 
 
 SG_EXPORTS = ("sg_conv3d_fwd", "sg_weight_prep", "sg_conv3d_bwd_weight_ws", "sg_conv3d_bwd_weight",
-              "sg_relu_bwd_cast", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_mse",
+              "sg_relu_bwd_cast", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_up2_cat_fwd", "sg_mse",
               "sg_adam", "sg_pack", "sg_unpack", "sg_lift")
 
 _sl = None
@@ -57,7 +57,7 @@ def lib():
             "sg_conv3d_bwd_weight": [V, V, i32, i32, vp, vp, vp, i64, vp],
             "sg_relu_bwd_cast": [V, V, V, vp],
             "sg_pool2_fwd": [V, V, vp], "sg_pool2_bwd": [V, V, i32, vp],
-            "sg_up2_fwd": [V, V, vp], "sg_up2_bwd": [V, V, i32, vp],
+            "sg_up2_fwd": [V, V, vp], "sg_up2_bwd": [V, V, i32, vp], "sg_up2_cat_fwd": [V, V, V, vp],
             "sg_mse": [V, V, V, vp, vp],
             "sg_adam": [vp, vp, vp, vp, i64, f32, f32, f32, f32, i64, vp],
             "sg_pack": [vp, i32, i32, i32, i32, i32, i32, i32, vp, V, V, i32, vp],
@@ -166,6 +166,10 @@ class UNet:
         self.x_in = A(0, CIN)
         self.x32 = A(0, NF, torch.float32)          # input fields (FP32) for the residual
         self.a1, self.cat1, self.d1a, self.d1b = A(0, c1), A(0, c2 + c1), A(0, c1), A(0, c1)
+        # the full-resolution skip output in a buffer of its own: written and
+        # pooled contiguously, copied into cat1 by the upsampling that fills the
+        # rest of cat1's rows (whole-line writes; the backward reads cat1)
+        self.s1 = A(0, c1)
         self.p1, self.a2, self.cat2, self.d2a, self.d2b = A(1, c1), A(1, c2), A(1, c3 + c2), A(1, c2), A(1, c2)
         self.p2, self.a3, self.cat3, self.d3a, self.d3b = A(2, c2), A(2, c3), A(2, c4 + c3), A(2, c3), A(2, c3)
         self.p3, self.a4, self.b4 = A(3, c3), A(3, c4), A(3, c4)
@@ -193,8 +197,8 @@ class UNet:
         L, c1, c2, c3, c4, pm = self.L, *WIDTHS, self.pmask
         v = view
         L["e1a"].fwd(v(self.x_in), v(self.a1), pmask=pm)
-        L["e1b"].fwd(v(self.a1), v(self.cat1, c2, c1), pmask=pm)
-        _chk(lib().sg_pool2_fwd(C.byref(v(self.cat1, c2, c1)), C.byref(v(self.p1)), _stream()), "pool1")
+        L["e1b"].fwd(v(self.a1), v(self.s1), pmask=pm)
+        _chk(lib().sg_pool2_fwd(C.byref(v(self.s1)), C.byref(v(self.p1)), _stream()), "pool1")
         L["e2a"].fwd(v(self.p1), v(self.a2), pmask=pm)
         L["e2b"].fwd(v(self.a2), v(self.cat2, c3, c2), pmask=pm)
         _chk(lib().sg_pool2_fwd(C.byref(v(self.cat2, c3, c2)), C.byref(v(self.p2)), _stream()), "pool2")
@@ -209,7 +213,8 @@ class UNet:
         _chk(lib().sg_up2_fwd(C.byref(v(self.d3b)), C.byref(v(self.cat2, 0, c3)), _stream()), "up2")
         L["d2a"].fwd(v(self.cat2), v(self.d2a), pmask=pm)
         L["d2b"].fwd(v(self.d2a), v(self.d2b), pmask=pm)
-        _chk(lib().sg_up2_fwd(C.byref(v(self.d2b)), C.byref(v(self.cat1, 0, c2)), _stream()), "up1")
+        _chk(lib().sg_up2_cat_fwd(C.byref(v(self.d2b)), C.byref(v(self.s1)), C.byref(v(self.cat1)), _stream()),
+             "up1")
         L["d1a"].fwd(v(self.cat1), v(self.d1a), pmask=pm)
         L["d1b"].fwd(v(self.d1a), v(self.d1b), pmask=pm)
         self.out32.copy_(self.x32)

@@ -29,6 +29,17 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(B.EXPORTS)
 
 
+def test_surrogate_library_exports_every_declared_symbol():
+    from paper_1904_03618_amd import surrogate as S
+    txt = open(os.path.join(ROOT, "include", "lbcg_surrogate.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = set(re.findall(r"\b(sg_[a-z0-9_]+)\s*\(", txt))
+    L = B.load()
+    for n in names:
+        assert hasattr(L, n), n
+    assert names == set(S.SG_EXPORTS)
+
+
 def test_struct_layout_matches_header():
     # 6 ints + 10 doubles (5 pairs) + 5 doubles + 7 doubles + 2 ints + 6 doubles (wall velocities)
     assert C.sizeof(B.lbcg_case) == 6 * 4 + 10 * 8 + 5 * 8 + 7 * 8 + 2 * 4 + 6 * 8

@@ -126,6 +126,17 @@ def test_elementwise_layers():
     up = torch.zeros_like(xt)
     assert L.sg_up2_fwd(C.byref(S.view(p)), C.byref(S.view(up)), st) == 0
     assert np.array_equal(up.float().cpu().numpy(), R.up2(p.float().cpu().numpy()))
+    # upsampling into a concatenation: [up2(coarse) | skip] per position, with
+    # the destination a channel slice of a wider buffer
+    coarse, _ = bft(rng.standard_normal((2, 2, 3, 4, 16)))
+    skip, _ = bft(rng.standard_normal((2, 4, 6, 8, 8)))
+    wide = torch.full((2, 4, 6, 8, 40), 7.0, dtype=torch.bfloat16, device="cuda")
+    assert L.sg_up2_cat_fwd(C.byref(S.view(coarse)), C.byref(S.view(skip)), C.byref(S.view(wide, 8, 24)), st) == 0
+    w = wide.float().cpu().numpy()
+    assert np.array_equal(w[..., 8:24], R.up2(coarse.float().cpu().numpy()))
+    assert np.array_equal(w[..., 24:32], skip.float().cpu().numpy())
+    assert (w[..., :8] == 7.0).all() and (w[..., 32:] == 7.0).all()
+    assert L.sg_up2_cat_fwd(C.byref(S.view(coarse)), C.byref(S.view(skip)), C.byref(S.view(wide, 0, 32)), st) != 0
     g = f32t(rng.standard_normal((2, 2, 3, 4, 8)))
     gx = f32t(np.ones((2, 4, 6, 8, 8)))
     assert L.sg_pool2_bwd(C.byref(S.view(g)), C.byref(S.view(gx)), 1, st) == 0
