@@ -40,6 +40,32 @@ def test_surrogate_library_exports_every_declared_symbol():
     assert names == set(S.SG_EXPORTS)
 
 
+def test_surrogate_entry_points_reject_mismatched_views():
+    """Shape and layout checks run on the host before any launch (the view
+    pointers here are host memory and are never dereferenced)."""
+    from paper_1904_03618_amd import surrogate as S
+    L = S.lib()
+    buf = np.zeros(1 << 16, dtype=np.float32)
+    p = buf.ctypes.data
+
+    def v(n, d, h, w, ctot, coff=0, c=None):
+        return C.byref(S.sg_view(p, n, d, h, w, ctot, coff, ctot - coff if c is None else c, 0))
+
+    EINVAL = -1
+    # pooling and upsampling: the coarse side must be half the fine side, same channels
+    assert L.sg_pool2_fwd(v(1, 4, 4, 4, 8), v(1, 2, 2, 3, 8), None) == EINVAL
+    assert L.sg_up2_fwd(v(1, 2, 2, 2, 8), v(1, 4, 4, 4, 16), None) == EINVAL
+    # upsampling into a concatenation: y's channels = x's + skip's, skip at y's positions
+    assert L.sg_up2_cat_fwd(v(1, 2, 2, 2, 16), v(1, 4, 4, 4, 8), v(1, 4, 4, 4, 32), None) == EINVAL
+    assert L.sg_up2_cat_fwd(v(1, 2, 2, 2, 16), v(1, 4, 4, 2, 8), v(1, 4, 4, 4, 24), None) == EINVAL
+    assert L.sg_up2_cat_fwd(v(1, 2, 2, 2, 16), v(1, 4, 4, 4, 8), v(1, 4, 4, 3, 24), None) == EINVAL
+    assert L.sg_up2_cat_fwd(v(1, 2, 2, 2, 12), v(1, 4, 4, 4, 12), v(1, 4, 4, 4, 24), None) == EINVAL
+    # convolution: output channels a multiple of 16, kernel 1 or 3, an output view
+    assert L.sg_conv3d_fwd(v(1, 4, 4, 4, 8), p, None, 24, 3, 0, 0, v(1, 4, 4, 4, 24), None, 0, None) == EINVAL
+    assert L.sg_conv3d_fwd(v(1, 4, 4, 4, 8), p, None, 16, 5, 0, 0, v(1, 4, 4, 4, 16), None, 0, None) == EINVAL
+    assert L.sg_conv3d_fwd(v(1, 4, 4, 4, 8), p, None, 16, 3, 0, 0, None, None, 0, None) == EINVAL
+
+
 def test_struct_layout_matches_header():
     # 6 ints + 10 doubles (5 pairs) + 5 doubles + 7 doubles + 2 ints + 6 doubles (wall velocities)
     assert C.sizeof(B.lbcg_case) == 6 * 4 + 10 * 8 + 5 * 8 + 7 * 8 + 2 * 4 + 6 * 8
