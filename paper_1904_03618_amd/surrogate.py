@@ -322,13 +322,15 @@ LEVEL = {"e1": 0, "d1": 0, "he": 0, "e2": 1, "d2": 1, "e3": 2, "d3": 2, "e4": 3}
 def flops(net):
     """Algorithmic FLOPs (2 per multiply-add) of one forward pass and of one
     training step (forward, weight gradients, data gradients of every layer
-    but the first) of the network at its buffer shape."""
+    but the first) of the network at its buffer shape.  The first layer counts
+    its NF real input channels, not the zero channels that pad them to CIN."""
     n, d, h, w = net.shape
     fwd = bwd_w = bwd_x = 0
     for l in net.layers:
         lv = LEVEL[l.name[:2]]
         P = n * (d >> lv) * (h >> lv) * (w >> lv)
-        f = 2 * P * l.co * l.k ** 3 * l.ci
+        ci = NF if l.name == "e1a" else l.ci
+        f = 2 * P * l.co * l.k ** 3 * ci
         fwd += f
         bwd_w += f
         if l.name != "e1a":
