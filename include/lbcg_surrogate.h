@@ -6,7 +6,9 @@
  *
  * Tensors.  Activations are channels-last (N, D, H, W, C) arrays; a view
  * names a channel slice [coff, coff + c) of an array with ctot channels per
- * position, so skip connections concatenate channels without copies.
+ * position, so skip connections can concatenate channels without copies
+ * (sg_up2_cat_fwd instead writes a concatenation in whole rows, which is
+ * faster where the two parts would otherwise be written as partial lines).
  * Activations are BF16 (MFMA operands), gradients FP32.  Convolution
  * weights are [co][k^3 * ci] (tap-major, channel-minor, tap = (dz+1)*9 +
  * (dy+1)*3 + (dx+1) for k = 3); k is 1 or 3; stride 1; padding 1 for k = 3,
