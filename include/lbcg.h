@@ -228,10 +228,12 @@ int32_t lbcg_storage_bytes(const lbcg_handle *h);
  * bad handle).  lbcg_checkpoint_save synchronises the handle's stream and
  * copies the image into caller-owned HOST memory of at least that size.
  * lbcg_checkpoint_load restores an image into a handle created with the same
- * case shapes and storage format (parameters other than the shapes are the
- * handle's own); the next steps then continue bit for bit as the saved handle
- * would have.  Errors: LBCG_ESTATE, LBCG_EINVAL (NULL buffer, too small, or an
- * image of another shape/format), LBCG_EDEVICE. */
+ * case shapes, in the same case order, and storage format (the image records
+ * every case's extents and array offsets and the load compares them;
+ * parameters other than the shapes are the handle's own); the next steps then
+ * continue bit for bit as the saved handle would have.  Errors: LBCG_ESTATE,
+ * LBCG_EINVAL (NULL buffer, too small, or an image of other case extents,
+ * case order or storage format), LBCG_EDEVICE. */
 int64_t lbcg_checkpoint_bytes(const lbcg_handle *h);
 int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes);
 int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes);

@@ -441,18 +441,29 @@ int check_handle(const lbcg_handle *h)
 
 }  // namespace
 
-// Checkpoint image: header, then the current level's populations of every
+// Checkpoint image: header, one descriptor per case (extents, array stride
+// and offsets, in case order), then the current level's populations of every
 // case (pop[cur]) and the writers' densities of that level (rho2[(t+1)&1]).
 namespace {
 struct CkptHeader {
     char magic[8];
     int64_t version, storage, ncases, total_pop, total_nodes, steps;
 };
+struct CkptCase {
+    int64_t nx, ny, nz, NS, pop_off, node_off;
+};
 constexpr char kMagic[8] = {'L', 'B', 'C', 'G', 'C', 'K', 'P', 'T'};
+constexpr int64_t kCkptVersion = 3;
+
+CkptCase ckpt_case(const DevCase &d)
+{
+    return CkptCase{d.nx, d.ny, d.nz, d.NS, d.pop_off, d.node_off};
+}
 
 int64_t ckpt_bytes(const lbcg_handle *h)
 {
-    return (int64_t)sizeof(CkptHeader) + (int64_t)h->elem * h->total_pop + (int64_t)sizeof(float2) * h->total_nodes;
+    return (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(CkptCase) * h->ncases + (int64_t)h->elem * h->total_pop +
+           (int64_t)sizeof(float2) * h->total_nodes;
 }
 }  // namespace
 
@@ -773,7 +784,7 @@ int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes)
     if (!host || bytes < ckpt_bytes(h)) return fail(LBCG_EINVAL, "checkpoint buffer NULL or too small");
     CkptHeader hd;
     std::memcpy(hd.magic, kMagic, 8);
-    hd.version = 2;
+    hd.version = kCkptVersion;
     hd.storage = h->storage;
     hd.ncases = h->ncases;
     hd.total_pop = h->total_pop;
@@ -782,6 +793,11 @@ int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes)
     char *p = static_cast<char *>(host);
     std::memcpy(p, &hd, sizeof hd);
     p += sizeof hd;
+    for (int c = 0; c < h->ncases; ++c) {
+        const CkptCase cc = ckpt_case(h->dc[c]);
+        std::memcpy(p, &cc, sizeof cc);
+        p += sizeof cc;
+    }
     HIPCHK(hipStreamSynchronize(h->stream));
     HIPCHK(hipMemcpy(p, h->pop[h->cur], (size_t)h->elem * h->total_pop, hipMemcpyDeviceToHost));
     p += (size_t)h->elem * h->total_pop;
@@ -796,12 +812,21 @@ int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes)
     if (!host || bytes < (int64_t)sizeof(CkptHeader)) return fail(LBCG_EINVAL, "checkpoint buffer NULL or too small");
     CkptHeader hd;
     std::memcpy(&hd, host, sizeof hd);
-    if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != 2) return fail(LBCG_EINVAL, "not a checkpoint image");
+    if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != kCkptVersion)
+        return fail(LBCG_EINVAL, "not a checkpoint image");
     if (hd.storage != h->storage || hd.ncases != h->ncases || hd.total_pop != h->total_pop ||
         hd.total_nodes != h->total_nodes || hd.steps < 0)
         return fail(LBCG_EINVAL, "checkpoint of another case shape or storage format");
     if (bytes < ckpt_bytes(h)) return fail(LBCG_EINVAL, "checkpoint buffer too small");
     const char *p = static_cast<const char *>(host) + sizeof hd;
+    for (int c = 0; c < h->ncases; ++c) {
+        CkptCase cc;
+        std::memcpy(&cc, p, sizeof cc);
+        p += sizeof cc;
+        const CkptCase mine = ckpt_case(h->dc[c]);
+        if (std::memcmp(&cc, &mine, sizeof cc) != 0)
+            return fail(LBCG_EINVAL, "checkpoint case " + std::to_string(c) + " has other extents or layout");
+    }
     HIPCHK(hipStreamSynchronize(h->stream));
     h->steps = hd.steps;
     h->cur = (int)(hd.steps & 1);       // the handle keeps pop[steps & 1] as the current level

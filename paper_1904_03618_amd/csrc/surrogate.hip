@@ -886,16 +886,22 @@ int sg_conv3d_fwd(const sg_view *x, const void *w, const float *bias, int32_t co
         hipStream_t st = (hipStream_t)hip_stream;
         const sg_view yv = y ? *y : none, y32v = y32 ? *y32 : none;
         const bool deep = x->c % 32 != 0 && x->d % 8 == 0;   // few or odd channel counts: two planes per wave
+        // a 32-channel chunk stages 1, 2 or 4 eight-channel groups per position;
+        // an input channel count of 24 mod 32 would leave a last chunk of 3
+        // groups, so those layers stage 16-channel chunks
+        const bool ct16 = x->c % 32 == 24;
         // two planes per wave also for 32-channel chunks when that still leaves
         // at least 512 workgroups (large layers: less halo per output; measured
         // on the U-Net, smaller layers lose from the fewer workgroups)
         const bool big = x->d % 8 == 0 && P / (BX * BY * 8) * (co / 32) >= 512;
         if (co % 32 == 0) {
             if (deep) launch_brick<2, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+            else if (ct16) launch_brick<2, 1, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
             else if (big) launch_brick<2, 2, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
             else launch_brick<2, 1, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
         } else {
             if (deep) launch_brick<1, 2, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
+            else if (ct16) launch_brick<1, 1, 16>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
             else launch_brick<1, 1, 32>(x, w, bias, co, periodic_mask, relu, yv, y32v, accumulate, st);
         }
         return status();
@@ -959,16 +965,18 @@ int64_t sg_conv3d_bwd_weight_ws(const sg_view *dy, int32_t ci, int32_t k)
     return bwd_plan(dy, ci, k).ws_floats * (int64_t)sizeof(float);
 }
 
-int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw, float *db,
-                         float *ws, int64_t ws_bytes, void *hip_stream)
+static bool bwd_weight_args(const sg_view *x, const sg_view *dy, int32_t k, const float *dw)
 {
-    if (!mfma_view(x) || !ok_view(dy) || dy->ctot % 8 || dy->coff % 8 || dy->c > 256 || !same_pos(x, dy) || !dw ||
-        !ws || (k != 1 && k != 3))
-        return SG_EINVAL;
+    return mfma_view(x) && ok_view(dy) && dy->ctot % 8 == 0 && dy->coff % 8 == 0 && dy->c <= 256 && same_pos(x, dy) &&
+           dw && (k == 1 || k == 3);
+}
+
+// The weight-gradient kernels with the per-group partial sums in ws (at least
+// b.ws_floats floats).
+static int bwd_weight_launch(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw,
+                             float *db, float *ws, const BwdPlan &b, hipStream_t st)
+{
     const int ci = x->c, co = dy->c;
-    const BwdPlan b = bwd_plan(dy, ci, k);
-    if (ws_bytes < b.ws_floats * (int64_t)sizeof(float)) return SG_EINVAL;
-    hipStream_t st = (hipStream_t)hip_stream;
     const dim3 grid(b.groups, b.co_pad / (16 * b.nob), b.cblocks);
     float *wsb = db ? ws + b.bias_off : nullptr;
     if (b.nob == 2)
@@ -987,7 +995,17 @@ int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t
         hipLaunchKernelGGL(k_reduce_final, dim3(grid_for(co)), dim3(256), 0, st, (const float *)(ws + b.tmpb_off), b.S,
                            (int64_t)co, db);
     }
+    (void)ci;
     return status();
+}
+
+int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw, float *db,
+                         float *ws, int64_t ws_bytes, void *hip_stream)
+{
+    if (!bwd_weight_args(x, dy, k, dw) || !ws) return SG_EINVAL;
+    const BwdPlan b = bwd_plan(dy, x->c, k);
+    if (ws_bytes < b.ws_floats * (int64_t)sizeof(float)) return SG_EINVAL;
+    return bwd_weight_launch(x, dy, k, periodic_mask, dw, db, ws, b, (hipStream_t)hip_stream);
 }
 
 int sg_relu_bwd_cast(const sg_view *dx, const sg_view *y, const sg_view *dyb, void *hip_stream)

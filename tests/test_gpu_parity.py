@@ -103,6 +103,10 @@ def _cases():
         "paper_fluids_32_offcentre": lambda: _offcentre(W.paper_fluids_droplet(32, 8.0)),
         "galilean_24": lambda: W.galilean_droplet(24, 5.0, seed=7),
         "channel_8x8x32_visc10": lambda: W.layered_channel(8, 8, 32, ratio=1.0, visc_ratio=10.0, G=1e-5),
+        # density and viscosity ratio 10: a steady, plane-uniform state in which
+        # every node of a plane rounds alike; the deviation storage keeps that
+        # rounding from accumulating, so the standard tolerances hold
+        "channel_8x8x32_ratio10_visc10": lambda: W.layered_channel(8, 8, 32, ratio=10.0, visc_ratio=10.0, G=1e-5),
         "rayleigh_taylor_12": lambda: W.rayleigh_taylor(12, g=2e-4),
         "walls_wetting_force": lambda: W.random_state_case(14, 12, 11, seed=5, bc=(0, 0, 1),
                                                            theta=(65.0, 140.0), force=(2e-5, 0, -1e-5)),
@@ -170,22 +174,6 @@ def test_degenerate_extents_in_one_batch():
     cases = list(_degenerate_cases().values())
     for (p, fl), g in zip(cases, gpu_run(cases, 200)):
         assert_parity("batch", g, oracle_run(p, fl, 200), p)
-
-
-def test_channel_density_ratio_10():
-    """Layered channel, density and viscosity ratio 10 (rho_R^in = 10).  This
-    steady, plane-uniform state makes FP32 rounding of the O(10) populations
-    coherent from step to step (every node of a plane rounds alike), so the
-    density error grows linearly, about one FP32 ulp of rho_R per step; the
-    velocity stays within 1e-6.  Checked at 50 steps with the standard
-    tolerances and at 500 steps on the velocity."""
-    p, fl = W.layered_channel(8, 8, 32, ratio=10.0, visc_ratio=10.0, G=1e-5)
-    assert_parity("channel_ratio10_50", gpu_run([(p, fl)], 50)[0], oracle_run(p, fl, 50), p)
-    g, o = gpu_run([(p, fl)], 500)[0], oracle_run(p, fl, 500)
-    e = max_err(g, o)
-    report("channel_ratio10_500", e)
-    assert max(e["ux"], e["uy"], e["uz"]) <= TOL_U
-    assert e["rhoR"] <= 500 * 1e-6 * p["rho_in"][0]
 
 
 @pytest.mark.parametrize("maker", [lambda: W.static_droplet(32, 8.0), lambda: W.paper_fluids_droplet(32, 8.0)],
@@ -373,7 +361,7 @@ def test_checkpoint_resume_is_bitwise(storage):
     """N steps, save, N more steps equals: a fresh handle that loads the image
     and runs N steps, and the same handle reloaded and run again (with graph
     replays and an odd step count in between), bit for bit; images of another
-    shape are rejected."""
+    shape, or of the same boxes in another order, are rejected."""
     import torch
     from paper_1904_03618_amd import lbcg as B
     cases = [W.random_state_case(12, 10, 9, seed=71, bc=(0, 0, 1), theta=(70.0, 120.0)),
@@ -401,6 +389,13 @@ def test_checkpoint_resume_is_bitwise(storage):
                 B.lbcg_checkpoint_load(hc, img)
         finally:
             B.lbcg_free(hc)
+        # the same two boxes in the other order: equal totals, other layout
+        hd = B.lbcg_init(cases[::-1], storage=storage)
+        try:
+            with pytest.raises(B.LbcgError):
+                B.lbcg_checkpoint_load(hd, img)
+        finally:
+            B.lbcg_free(hd)
     finally:
         B.lbcg_free(ha)
         B.lbcg_free(hb)

@@ -47,6 +47,9 @@ def close(got, want, rtol=2e-5):
     (3, 7, (2, 8, 4, 32), 64, 16, 48, 32),
     (3, 3, (1, 4, 8, 16), 192, 0, 192, 64),
     (3, 6, (1, 8, 8, 16), 16, 0, 16, 16),
+    # 24 mod 32 input channels on bricks of one plane per wave (16-channel chunks)
+    (3, 0, (1, 4, 4, 16), 24, 0, 24, 16),
+    (3, 5, (1, 4, 4, 16), 64, 8, 56, 32),
 ])
 def test_conv_forward_data_and_weight_gradients(k, pmask, shape, ctot, coff, ci, co):
     import torch
