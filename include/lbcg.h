@@ -66,6 +66,10 @@ extern "C" {
  *             high wall of the wall axis (90 = neutral);
  *   improved  1: improved model (Eq. 18 equilibrium + correction term Eq. 45);
  *             0: the same MRT model without both improvements;
+ *   meq4      rows 16-18 of the moment equilibria: 0 = M f^eq (the definition
+ *             the text gives for m^eq, and the default), 1 = the rows as the
+ *             Appendix prints them (2 rho_k c^2 (u_a^2 + u_b^2) in place of
+ *             the 3 rho_k (u_a^2 + u_b^2) of M f^eq); other values LBCG_EINVAL;
  *   wall_u    velocity of the low and high wall of the wall axis (moving
  *             plates, Sec. IV.A); tangential only (the component along the
  *             wall axis must be 0) and zero when no axis is a wall.  A
@@ -90,7 +94,7 @@ typedef struct lbcg_case {
     double grav[3];
     double rho_ref;
     int32_t improved;
-    int32_t reserved;
+    int32_t meq4;
     double wall_u[2][3];
 } lbcg_case;
 

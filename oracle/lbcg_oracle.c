@@ -55,6 +55,7 @@ typedef struct {
     double grav[3];         /* buoyancy: F += (rho - rho_ref) * grav */
     double rho_ref;
     int improved;           /* 1: Eq. (18) + correction term; 0: Eq. (6), no correction */
+    int meq4;               /* rows 16-18 of m^eq: 0 = M f^eq (default), 1 = the Appendix as printed */
     double wall_u[2][3];    /* velocity of the low / high wall of the wall axis (tangential) */
 } orc_params;
 
@@ -220,6 +221,16 @@ void orc_collide_color(const orc_params *p, int k, const double *f, double rho_k
     matvec(MM, f, m);
     feq_k(p, k, rho_k, u, feq);
     matvec(MM, feq, meq);                       /* m^{k,eq} = M f^{k,eq} (after Eq. 53/44) */
+    if (p->meq4) {
+        /* The Appendix prints rows 16-18 of m^{k,eq} with 2 rho_k c^2 (u_a^2 + u_b^2)
+         * where M f^{k,eq} gives 3 rho_k (u_a^2 + u_b^2); this switch takes the
+         * printed rows instead of M f^eq (c = 1). */
+        double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        double base = rho_k * (1.0 - p->alpha[k] - uu);
+        meq[16] = (base + 2.0 * rho_k * (u[0] * u[0] + u[1] * u[1])) / 6.0;
+        meq[17] = (base + 2.0 * rho_k * (u[0] * u[0] + u[2] * u[2])) / 6.0;
+        meq[18] = (base + 2.0 * rho_k * (u[1] * u[1] + u[2] * u[2])) / 6.0;
+    }
     for (int r = 0; r < Q; ++r) C[r] = 0.0;
     if (p->improved) {                          /* Eq. (45) */
         C[4] = Qk[0] + Qk[1] + Qk[2];

@@ -44,6 +44,7 @@ class _Params(C.Structure):
         ("tau_e", C.c_double), ("tau_q", C.c_double), ("tau_pi", C.c_double),
         ("force", C.c_double * 3), ("grav", C.c_double * 3), ("rho_ref", C.c_double),
         ("improved", C.c_int),
+        ("meq4", C.c_int),
         ("wall_u", (C.c_double * 3) * 2),
     ]
 
@@ -79,7 +80,8 @@ def lib():
 
 PARAM_DEFAULTS = dict(bc=(0, 0, 0), theta_deg=(90.0, 90.0), beta=0.5, delta=0.98,
                       tau_e=1.0, tau_q=1.0, tau_pi=1.0, force=(0.0, 0.0, 0.0),
-                      grav=(0.0, 0.0, 0.0), rho_ref=0.0, improved=1, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+                      grav=(0.0, 0.0, 0.0), rho_ref=0.0, improved=1, meq4=0,
+                      wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
 
 
 def make_params(p: dict) -> _Params:
@@ -94,6 +96,7 @@ def make_params(p: dict) -> _Params:
     for name in ("beta", "delta", "tau_e", "tau_q", "tau_pi", "rho_ref"):
         setattr(s, name, float(q[name]))
     s.improved = int(q["improved"])
+    s.meq4 = int(q["meq4"])
     for side in range(2):
         s.wall_u[side][:] = [float(v) for v in q["wall_u"][side]]
     return s

@@ -138,7 +138,8 @@ struct DevCase {
     float neg_tol[2];            // stability check: rho_k < neg_tol[k] is unstable
     float uw[2][3];              // velocity of the low / high wall (tangential)
     float wg[2][2];              // wall gain per colour for axis / diagonal links, per unit rho_k (e_i . U_w)
-    int moving, pad1;            // 1 when a wall velocity is nonzero
+    int moving;                  // 1 when a wall velocity is nonzero
+    float c16;                   // rows 16-18 of m^eq: coefficient of rho (u_a^2 + u_b^2)
 };
 
 struct StepArgs {

@@ -102,6 +102,30 @@ __device__ inline Coord make_coord(DC &C, int node)
     return c;
 }
 
+// The same from known coordinates (no division).
+template <int WL = WALLS_ANY>
+__device__ inline Coord make_coord_xyz(DC &C, int x, int y, int z)
+{
+    Coord c;
+    const int nxy = C.nx * C.ny;
+    c.x = x; c.y = y; c.z = z;
+    c.node = x + C.nx * y + nxy * z;
+    c.o[0][0] = c.x == 0 ? C.nx - 1 : -1;
+    c.o[0][1] = 0;
+    c.o[0][2] = c.x == C.nx - 1 ? 1 - C.nx : 1;
+    c.o[1][0] = c.y == 0 ? nxy - C.nx : -C.nx;
+    c.o[1][1] = 0;
+    c.o[1][2] = c.y == C.ny - 1 ? C.nx - nxy : C.nx;
+    c.o[2][0] = c.z == 0 ? C.N - nxy : -nxy;
+    c.o[2][1] = 0;
+    c.o[2][2] = c.z == C.nz - 1 ? nxy - C.N : nxy;
+    constexpr bool xy = WL == WALLS_ANY, zz = WL != WALLS_NONE;
+    c.lo[0] = xy && C.wall == 0 && c.x == 0; c.hi[0] = xy && C.wall == 0 && c.x == C.nx - 1;
+    c.lo[1] = xy && C.wall == 1 && c.y == 0; c.hi[1] = xy && C.wall == 1 && c.y == C.ny - 1;
+    c.lo[2] = zz && C.wall == 2 && c.z == 0; c.hi[2] = zz && C.wall == 2 && c.z == C.nz - 1;
+    return c;
+}
+
 // Node at x + (X, Y, Z) with periodic wrap (X, Y, Z in {-1, 0, 1}).
 template <int X, int Y, int Z>
 __device__ inline int neighbour(const Coord &c)
@@ -211,6 +235,88 @@ __device__ inline void pull_all(const StepArgs &a, DC &C, const Coord &c, const 
         pull_one<ST, MV, CPP, I>(a, C, c, own, s, eR, eB);
         pull_all<ST, MV, CPP, I + 1>(a, C, c, own, s, eR, eB);
     }
+}
+
+// The same pull with the writers' densities read from an LDS copy of the
+// stored-density planes z-1, z, z+1 (rl[0..2], row length RW; ri: the node's
+// index in a plane) instead of from memory.  A bounce-back lane takes its own
+// density (its slot read is discarded), as the memory form does.
+constexpr int RH = 3;                    // halo of the stored-density planes around a fused tile
+constexpr int RW = 16 + 2 * RH, RREG = RW * RW;
+
+// Issue phase: the 19 population loads of a node, all in flight at once.
+template <int ST, int CPP, int I = 0>
+__device__ inline void pull_issue(const StepArgs &a, DC &C, const Coord &c, typename Storage<ST>::P (&v)[Q])
+{
+    if constexpr (I < Q) {
+        using P = typename Storage<ST>::P;
+        constexpr int F = pair_first<I>(), W = I == 0 ? 1 : 2;
+        const size_t NS = (size_t)C.NS;
+        const P *base = reinterpret_cast<const P *>(a.fin) + C.pop_off / 2;
+        const bool bb = bounce<I>(c);
+        const uint32_t si = (uint32_t)(bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c));
+        constexpr bool hi_own = I != F, hi_opp = opp(I) != F;
+        const bool hi = bb ? hi_opp : hi_own;
+        const uint32_t e = si + (hi ? (uint32_t)NS : 0u);
+        v[I] = buf_ld<P, CPP>(rsrc(base + (size_t)F * NS, W * NS * sizeof(P)), e * (uint32_t)sizeof(P));
+        pull_issue<ST, CPP, I + 1>(a, C, c, v);
+    }
+}
+
+// Decode phase: deviations plus the writers' densities from the LDS plane
+// ring (as pull_one does with the densities from memory).
+template <int ST, bool MV, int I = 0>
+__device__ inline void pull_decode(const StepArgs &a, DC &C, const Coord &c, const float2 own,
+                                   const float2 *const (&rl)[3], int ri, const typename Storage<ST>::P (&v)[Q],
+                                   NodeState &s, float &eR, float &eB)
+{
+    if constexpr (I < Q) {
+        using S = Storage<ST>;
+        const bool bb = bounce<I>(c);
+        const float dR = S::dec(v[I].r, a.inv_scale);
+        const float dB = S::dec(v[I].b, a.inv_scale);
+        const float2 pl = rl[1 - ez(I)][ri - ex(I) - RW * ey(I)];
+        const float2 ps = bb ? own : pl;
+        float tR = __builtin_fmaf(ps.x - own.x, C.phi[0][ecls(I)], dR);
+        float tB = __builtin_fmaf(ps.y - own.y, C.phi[1][ecls(I)], dB);
+        if constexpr (MV && I != 0) {
+            if (C.moving && bb) {
+                const float eu = wall_eu<I>(C, bounce_side<I>(c));
+                tR = __builtin_fmaf(eu * C.wg[0][ecls(I) - 1], own.x, tR);
+                tB = __builtin_fmaf(eu * C.wg[1][ecls(I) - 1], own.y, tB);
+            }
+        }
+        const float h = tR + tB;
+        s.h[I] = h;
+        eR += tR;
+        eB += tB;
+        if constexpr (ex(I) == 1) s.jx += h;
+        if constexpr (ex(I) == -1) s.jx -= h;
+        if constexpr (ey(I) == 1) s.jy += h;
+        if constexpr (ey(I) == -1) s.jy -= h;
+        if constexpr (ez(I) == 1) s.jz += h;
+        if constexpr (ez(I) == -1) s.jz -= h;
+        pull_decode<ST, MV, I + 1>(a, C, c, own, rl, ri, v, s, eR, eB);
+    }
+}
+
+template <int ST, bool MV, int CPP>
+__device__ inline void pull_node_rl(const StepArgs &a, DC &C, const Coord &c, const float2 *const (&rl)[3], int ri,
+                                    NodeState &s)
+{
+    typename Storage<ST>::P v[Q];
+    pull_issue<ST, CPP>(a, C, c, v);
+    __builtin_amdgcn_sched_barrier(0);       // every load issued before the first use
+    const float2 own = rl[1][ri];
+    float eR = 0.f, eB = 0.f;
+    s.jx = s.jy = s.jz = 0.f;
+    pull_decode<ST, MV>(a, C, c, own, rl, ri, v, s, eR, eB);
+    s.R[0] = own.x + eR;
+    s.R[1] = own.y + eB;
+    s.D[0] = s.R[0] - own.x;
+    s.D[1] = s.R[1] - own.y;
+    s.eta[0] = eR - s.D[0];
+    s.eta[1] = eB - s.D[1];
 }
 
 // CPP: cache policy of the population loads (streaming unless the same
@@ -424,7 +530,8 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     const float m15 = f[15] - f[16] + f[17] - f[18];
 
     // two-colour equilibria sum_k m^{k,eq} (Appendix rows 0-15; rows
-    // 16-18 as M f^eq) minus the rest-state moments; p = sum_k rho_k (c_s^k)^2
+    // 16-18 as M f^eq, or as the Appendix prints them) minus the rest-state
+    // moments; p = sum_k rho_k (c_s^k)^2
     const float p = s.R[0] * C.cs2[0] + s.R[1] * C.cs2[1];
     const float pe = s.eta[0] * C.cs2[0] + s.eta[1] * C.cs2[1];
     const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz, uu = uxx + uyy + uzz;
@@ -435,9 +542,10 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     const float p3 = C.improved ? p : rho * (1.0f / 3.0f);
     const float e10 = p3 * uy, e11 = p3 * ux, e12 = p3 * uz;
     const float e16b = (2.0f * pe - rho * uu) * (1.0f / 6.0f);
-    const float e16 = e16b + 0.5f * rho * (uxx + uyy);
-    const float e17 = e16b + 0.5f * rho * (uxx + uzz);
-    const float e18 = e16b + 0.5f * rho * (uyy + uzz);
+    const float rc16 = C.c16 * rho;
+    const float e16 = e16b + rc16 * (uxx + uyy);
+    const float e17 = e16b + rc16 * (uxx + uzz);
+    const float e18 = e16b + rc16 * (uyy + uzz);
 
     // correction term (Eq. 45), summed over the colours
     float c4 = 0.f, c5 = 0.f, c6 = 0.f;
@@ -588,19 +696,26 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 }
 
 // ---------------------------------------------------------------- k_fused
-// Single-pass step.  A workgroup owns an FTX x FTY column of nodes over a
-// chunk of z-planes and marches up the chunk.  For each plane it pulls the
-// populations of the tile and of its one-node x-y halo and writes their aux
-// values (rho^N, Qbar) into a three-plane LDS ring; then it collides the plane
-// below with the colour-gradient and correction stencils read from LDS.  No
-// node state is held across the plane barrier: the aux pass pulls with
-// cacheable loads and the collision pulls the same populations again one plane
-// later, from L2 or the last-level cache, so register use stays that of the
-// collision pass.  Aux never goes to HBM.  Eligible cases: walls (if any) on z
-// with neutral wetting (cot theta = 0), where the ghost layer is the mirror of
-// the first layer with Qbar reflected oddly.
+// Single-pass step.  A workgroup owns an FTX x FTY tile of columns over a
+// chunk of z-planes and marches up the chunk; each lane owns one column.  For
+// plane z + 1 it pulls its own node, keeps the pulled state in registers and
+// writes the node's aux value (rho^N, Qbar) into a four-plane LDS ring; a
+// second round pulls the tile's one-node x-y halo for its aux values only.
+// After one barrier the lanes collide plane z with the colour-gradient and
+// correction stencils read from the ring, and the state of plane z + 1
+// becomes the next plane's.  Populations are read once per node (the halo
+// pulls of a tile's edge are the interior pulls of its neighbour, mostly
+// served by the caches) and aux values never go to memory.  Walls, if any,
+// lie on z: the ghost layer beyond a wall is computed in LDS from the first
+// layer (wetting rule, Qbar reflected about its wall value), which needs that
+// layer's phase field two nodes around the tile, so the wall layers are
+// pulled with a two-node halo.  The four ring slots let one barrier per plane
+// suffice: the slot written for plane z + 2 was last read by the collision of
+// plane z - 2, which every lane finished before the previous barrier.
 constexpr int FTX = 16, FTY = 16;
-constexpr int FRX = FTX + 2, FRY = FTY + 2, FREG = FRX * FRY;
+constexpr int FH = 2;                                  // halo width the ring can hold
+constexpr int FRX = FTX + 2 * FH, FRY = FTY + 2 * FH, FREG = FRX * FRY;
+constexpr int FSLOTS = 4;
 
 struct FusedArgs {
     StepArgs a;
@@ -609,65 +724,171 @@ struct FusedArgs {
     int zc;                      // planes per chunk
 };
 
-__device__ inline int ring_slot(int z) { return (z + 3) % 3; }
+__device__ inline int fslot(int z) { return (z + FSLOTS) & (FSLOTS - 1); }   // z >= -1
+__device__ inline int fidx(int rx, int ry) { return (rx + FH) + FRX * (ry + FH); }
 
-// aux value of a node from its pulled state
-__device__ inline float4 aux_value(DC &C, const NodeState &s)
+// aux value of a node from its pulled state; qs = sum_k rho_k (1 - 3 c_s^k^2)
+__device__ inline float4 aux_value(DC &C, const NodeState &s, float &qs)
 {
     const Macro m = macro(C, s);
-    const float qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
+    qs = s.R[0] * C.qc[0] + s.R[1] * C.qc[1];
     return make_float4(phase_field(C, s.R[0], s.R[1]), m.ux * qs, m.uy * qs, m.uz * qs);
 }
 
+__device__ inline int rslot(int z) { return (z + 4) & 3; }                 // z >= -4
+__device__ inline int ridx(int rx, int ry) { return (rx + RH) + RW * (ry + RH); }
+
+// Copy the stored densities of plane zl (the writers' densities of the level
+// being pulled) around the tile into the LDS plane ring: the tile plus RH
+// nodes on each side, which covers every pull source of the tile's nodes and
+// of its halo.  Planes beyond a wall are not copied (their pulls bounce back).
+// Split into the loads (two rounds of at most RREG = 484 entries, issued
+// together and early) and the LDS stores, so that their latency hides behind
+// the pulls issued in between.
+struct RhoStage { float2 v[2]; int d[2]; };
+
+__device__ inline RhoStage fused_stage_load(const StepArgs &a, DC &C, int zl, int x0, int y0, int ax, int ay,
+                                            bool walls)
+{
+    RhoStage r;
+    r.d[0] = r.d[1] = -1;
+    int zp = zl;
+    if (walls) {
+        if (zl < 0 || zl >= C.nz) return r;
+    } else {
+        zp = (zl + 4 * C.nz) % C.nz;
+    }
+    const float2 *src = a.rho_prev + C.node_off + (size_t)C.nx * C.ny * zp;
+    const int w = ax + 2 * RH, n = w * (ay + 2 * RH);
+    #pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e0 = (int)threadIdx.x + 256 * k;
+        const int e = min(e0, n - 1);                   // lanes past the region reload its last entry
+        const int ry = e / w, rx = e - ry * w;
+        // periodic wrap without branches (the region reaches RH < 4 nodes beyond the box)
+        const int gx = (x0 + rx - RH + 4 * C.nx) % C.nx, gy = (y0 + ry - RH + 4 * C.ny) % C.ny;
+        r.v[k] = src[gx + C.nx * gy];
+        r.d[k] = e0 < n ? rx + RW * ry : -1;
+    }
+    return r;
+}
+
+__device__ inline void fused_stage_store(float2 (*rring)[RREG], int zl, const RhoStage &r)
+{
+    float2 *dst = rring[rslot(zl)];
+    #pragma unroll
+    for (int k = 0; k < 2; ++k)
+        if (r.d[k] >= 0) dst[r.d[k]] = r.v[k];
+}
+
+// Pull node (x, y, zp) of the case (coordinates wrapped into the box; rx, ry
+// its position relative to the tile origin, zl its logical plane).
+template <int ST, bool MV, int WL>
+__device__ inline void fused_pull(const StepArgs &a, DC &C, float2 (*rring)[RREG], int x, int y, int zp, int rx,
+                                  int ry, int zl, NodeState &s)
+{
+    const Coord c = make_coord_xyz<WL>(C, x, y, zp);
+    const float2 *const rl[3] = {rring[rslot(zl - 1)], rring[rslot(zl)], rring[rslot(zl + 1)]};
+    pull_node_rl<ST, MV, CP_DEFAULT>(a, C, c, rl, ridx(rx, ry), s);
+}
+
+// Aux values of plane zp (0 <= zp < nz) into the ring slot of plane zl (zl =
+// zp, or zp -+ nz for the periodic neighbours of the chunk's end planes): the
+// lane's own node (pulled state kept in s), then the halo of width h (1, or 2
+// on a wall layer) pulled by the lanes of two consecutive waves, rotated by
+// plane.  On a wall layer of a case with moving walls the density factor qs
+// of Qbar goes to wq[side] for the ghost layer.
+template <int ST, bool MV, int WL>
+__device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], float2 (*rring)[RREG],
+                                   float (*wq)[FREG], int zl, int zp, int x0, int y0, int ax, int ay, int h,
+                                   bool active, int tx, int ty, NodeState &s)
+{
+    float4 *slot = ring[fslot(zl)];
+    const bool wlo = MV && C.wall == 2 && zp == 0, whi = MV && C.wall == 2 && zp == C.nz - 1;
+    float qs;
+    if (active) {
+        fused_pull<ST, MV, WL>(a, C, rring, x0 + tx, y0 + ty, zp, tx, ty, zl, s);
+        slot[fidx(tx, ty)] = aux_value(C, s, qs);
+        if (wlo) wq[0][fidx(tx, ty)] = qs;
+        if (whi) wq[1][fidx(tx, ty)] = qs;
+    }
+    const int w = ax + 2 * h, nrow = 2 * h * w, nh = nrow + 2 * h * ay;
+    const int e0 = ((int)threadIdx.x - 64 * (zl & 3) + 256) & 255;   // halo duty rotates over the waves
+    for (int e = e0; e < nh; e += 256) {
+        int rx, ry;
+        if (e < nrow) {
+            const int r = e / w;
+            rx = e - r * w - h;
+            ry = r < h ? r - h : ay + (r - h);
+        } else {
+            const int e1 = e - nrow, cc = e1 / ay;
+            ry = e1 - cc * ay;
+            rx = cc < h ? cc - h : ax + (cc - h);
+        }
+        // periodic wrap without branches (the halo may wrap more than once
+        // around a box narrower than itself, but reaches at most 2 nodes out)
+        const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
+        NodeState hs;
+        fused_pull<ST, MV, WL>(a, C, rring, gx, gy, zp, rx, ry, zl, hs);
+        slot[fidx(rx, ry)] = aux_value(C, hs, qs);
+        if (wlo) wq[0][fidx(rx, ry)] = qs;
+        if (whi) wq[1][fidx(rx, ry)] = qs;
+    }
+}
+
+// Ghost layer beyond the wall at side `side` (0: z = -1, 1: z = nz) over the
+// tile and its one-node halo, from the first layer's slot (which holds a
+// two-node halo): rho^N follows the wetting rule with the 2D isotropic
+// stencil, Qbar is reflected about its wall value (as k_ghost does).
+template <bool MV>
+__device__ inline void fused_ghost(DC &C, float4 (*ring)[FREG], float (*wq)[FREG], int side, int ax, int ay)
+{
+    const float4 *src = ring[fslot(side ? C.nz - 1 : 0)];
+    float4 *dst = ring[fslot(side ? C.nz : -1)];
+    const int w = ax + 2, n = w * (ay + 2);
+    for (int e = (int)threadIdx.x; e < n; e += 256) {
+        const int ry = e / w - 1, rx = e - (ry + 1) * w - 1;
+        float gb = 0.f, gc = 0.f;
+        #pragma unroll
+        for (int db = -1; db <= 1; ++db) {
+            #pragma unroll
+            for (int dc = -1; dc <= 1; ++dc) {
+                if (db == 0 && dc == 0) continue;
+                const float wgt = (db != 0 && dc != 0) ? (1.0f / 12.0f) : (1.0f / 3.0f);
+                const float v = src[fidx(rx + db, ry + dc)].x;
+                gb += wgt * (float)db * v;
+                gc += wgt * (float)dc * v;
+            }
+        }
+        const float4 s = src[fidx(rx, ry)];
+        const float gpar = sqrtf(gb * gb + gc * gc);
+        const float qw = MV && C.moving ? 2.0f * wq[side][fidx(rx, ry)] : 0.f;
+        dst[fidx(rx, ry)] = make_float4(s.x + C.cot[side] * gpar, qw * C.uw[side][0] - s.y, qw * C.uw[side][1] - s.z,
+                                        qw * C.uw[side][2] - s.w);
+    }
+}
+
 template <int I = 1>
-__device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int r, Stencil &st)
+__device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int tx, int ty, Stencil &st)
 {
     if constexpr (I < Q) {
         constexpr int X = ex(I), Y = ey(I), Z = ez(I);
         constexpr float w3 = ecls(I) == 1 ? (1.0f / 6.0f) : (1.0f / 12.0f);
-        const float4 v = ring[ring_slot(z + Z)][r + X + FRX * Y];
+        const float4 v = ring[fslot(z + Z)][fidx(tx + X, ty + Y)];
         if constexpr (X != 0) { st.gx += (X * w3) * v.x; st.Qx += (X * w3) * v.y; }
         if constexpr (Y != 0) { st.gy += (Y * w3) * v.x; st.Qy += (Y * w3) * v.z; }
         if constexpr (Z != 0) { st.gz += (Z * w3) * v.x; st.Qz += (Z * w3) * v.w; }
-        stencil_lds<I + 1>(ring, z, r, st);
+        stencil_lds<I + 1>(ring, z, tx, ty, st);
     }
 }
 
-// Aux values of plane zz (-1 <= zz <= nz) for the tile and its halo, or the
-// mirror of the first layer beyond a wall.
-template <int ST>
-__device__ inline void aux_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], int zz, int x0, int y0,
-                                 int ax, int ay)
-{
-    const int slot = ring_slot(zz);
-    const int tid = (int)threadIdx.x;
-    const int w = ax + 2, nreg = w * (ay + 2);
-    if (C.wall == 2 && (zz < 0 || zz >= C.nz)) {
-        const int from = ring_slot(zz < 0 ? 0 : C.nz - 1);
-        for (int e = tid; e < nreg; e += blockDim.x) {
-            const int r = e % w + FRX * (e / w);
-            const float4 v = ring[from][r];
-            ring[slot][r] = make_float4(v.x, -v.y, -v.z, -v.w);
-        }
-        return;
-    }
-    const int z = zz < 0 ? zz + C.nz : (zz >= C.nz ? zz - C.nz : zz);
-    for (int e = tid; e < nreg; e += blockDim.x) {
-        const int rx = e % w, ry = e / w;
-        int x = x0 + rx - 1, y = y0 + ry - 1;
-        x = x < 0 ? x + C.nx : (x >= C.nx ? x - C.nx : x);
-        y = y < 0 ? y + C.ny : (y >= C.ny ? y - C.ny : y);
-        const Coord c = make_coord(C, x + C.nx * (y + C.ny * z));
-        NodeState s;
-        pull_node<ST, false, CP_DEFAULT>(a, C, c, s);
-        ring[slot][rx + FRX * ry] = aux_value(C, s);
-    }
-}
-
-template <int ST>
+// WL: WALLS_NONE or WALLS_Z (cases with walls on other axes take the two-pass step).
+template <int ST, bool MV, int WL>
 __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
 {
-    __shared__ float4 ring[3][FREG];
+    __shared__ float4 ring[FSLOTS][FREG];
+    __shared__ float2 rring[4][RREG];
+    __shared__ float wq[MV ? 2 : 1][FREG];
     const StepArgs &a = fa.a;
     const TileRange tr = tile_range(fa.nftiles);
     const int tx = (int)threadIdx.x % FTX, ty = (int)threadIdx.x / FTX;
@@ -678,28 +899,47 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
         const int z1 = min(z0 + fa.zc, C.nz);
         const int ax = min(FTX, C.nx - x0), ay = min(FTY, C.ny - y0);
         const bool active = tx < ax && ty < ay;
-        const int r = (tx + 1) + FRX * (ty + 1);
-        __syncthreads();                       // ring reuse across tiles
-        if (C.wall == 2 && z0 == 0) {
-            aux_plane<ST>(a, C, ring, 0, x0, y0, ax, ay);
-            __syncthreads();
-            aux_plane<ST>(a, C, ring, -1, x0, y0, ax, ay);
-        } else {
-            aux_plane<ST>(a, C, ring, z0 - 1, x0, y0, ax, ay);
-            aux_plane<ST>(a, C, ring, z0, x0, y0, ax, ay);
-        }
+        const bool walls = WL == WALLS_Z && C.wall == 2;
+        __syncthreads();                                   // both rings reused across tiles
+        // stored densities of the planes the prologue pulls read
+        for (int q = z0 - 2; q <= z0 + 1; ++q)
+            fused_stage_store(rring, q, fused_stage_load(a, C, q, x0, y0, ax, ay, walls));
+        __syncthreads();
+        NodeState cur, nxt;
+        // plane z0 (kept) and the plane below it (the top plane, for a
+        // periodic z at z0 = 0); at a bottom wall the ghost layer instead
+        fused_plane<ST, MV, WL>(a, C, ring, rring, wq, z0, z0, x0, y0, ax, ay,
+                                walls && (z0 == 0 || z0 == C.nz - 1) ? 2 : 1, active, tx, ty, cur);
+        if (!(walls && z0 == 0))
+            fused_plane<ST, MV, WL>(a, C, ring, rring, wq, z0 - 1, z0 == 0 ? C.nz - 1 : z0 - 1, x0, y0, ax, ay, 1,
+                                    active, tx, ty, nxt);
+        __syncthreads();
+        fused_stage_store(rring, z0 + 2, fused_stage_load(a, C, z0 + 2, x0, y0, ax, ay, walls));
+        if (walls && z0 == 0) fused_ghost<MV>(C, ring, wq, 0, ax, ay);
+        __syncthreads();
+        // Each plane: the aux values of plane z + 1 (or the top ghost layer),
+        // the stored densities of plane z + 3 for the next plane's pulls, one
+        // barrier, the collision of plane z.  The density slot written here
+        // was last read by the pulls of plane z, before the previous barrier.
         for (int z = z0; z < z1; ++z) {
-            aux_plane<ST>(a, C, ring, z + 1, x0, y0, ax, ay);
+            const int zn = z + 1;
+            const RhoStage rs = fused_stage_load(a, C, z + 3, x0, y0, ax, ay, walls);
+            if (walls && zn == C.nz) {
+                fused_ghost<MV>(C, ring, wq, 1, ax, ay);
+            } else {
+                const int zp = zn == C.nz ? 0 : zn;        // periodic wrap
+                fused_plane<ST, MV, WL>(a, C, ring, rring, wq, zn, zp, x0, y0, ax, ay,
+                                        walls && zp == C.nz - 1 ? 2 : 1, active, tx, ty, nxt);
+            }
+            fused_stage_store(rring, z + 3, rs);
             __syncthreads();
             if (active) {
                 const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
-                NodeState s;
-                pull_node<ST, false>(a, C, make_coord(C, node), s);
                 Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                stencil_lds(ring, z, r, st);
-                collide_node<ST>(a, C, node, s, st, ring[ring_slot(z)][r].x);
+                stencil_lds(ring, z, tx, ty, st);
+                collide_node<ST>(a, C, node, cur, st, ring[fslot(z)][fidx(tx, ty)].x);
             }
-            __syncthreads();
+            cur = nxt;
         }
     }
 }

@@ -115,6 +115,7 @@ int validate(const lbcg_case &c, int idx)
     if (std::fabs(pR - pB) > 1e-12 * std::max(pR, pB))
         return bad("pressure balance rho_R^in (1 - alpha_R) = rho_B^in (1 - alpha_B) violated");
     if (c.improved != 0 && c.improved != 1) return bad("improved must be 0 or 1");
+    if (c.meq4 != 0 && c.meq4 != 1) return bad("meq4 must be 0 or 1");
     int wall_axis = -1;
     for (int a = 0; a < 3; ++a)
         if (c.bc[a] == LBCG_WALL) wall_axis = a;
@@ -140,6 +141,8 @@ DevCase derive(const lbcg_case &c)
     d.NS = (d.N + 63) / 64 * 64;      // every array of a case starts on a 128-byte boundary (64 FP16 values)
     d.plane = d.wall < 0 ? 0 : d.N / (d.wall == 0 ? c.nx : (d.wall == 1 ? c.ny : c.nz));
     d.improved = c.improved;
+    // rows 16-18 of m^eq: rho (u_a^2 + u_b^2) times 1/2 (M f^eq) or 1/3 (the Appendix as printed)
+    d.c16 = c.meq4 ? (float)(1.0 / 3.0) : 0.5f;
     for (int k = 0; k < 2; ++k) {
         const double al = c.alpha[k], cs2 = 0.5 * (1.0 - al);
         d.rin_inv[k] = (float)(1.0 / c.rho_in[k]);
@@ -235,7 +238,12 @@ int launch_step(lbcg_handle *h, hipStream_t st)
     if (h->fused) {
         FusedArgs fa{a, h->d_ftiles, h->nftiles, h->zc};
         const int grid = h->persistent > 0 ? h->persistent : h->nftiles;
-        int rc = timed(h, 3, [&] { hipLaunchKernelGGL(k_fused<ST>, dim3(grid), dim3(FTX * FTY), 0, st, fa); });
+        int rc = timed(h, 3, [&] {
+            const dim3 g(grid), b(FTX * FTY);
+            if (h->moving) hipLaunchKernelGGL((k_fused<ST, true, WALLS_Z>), g, b, 0, st, fa);
+            else if (h->walls == WALLS_Z) hipLaunchKernelGGL((k_fused<ST, false, WALLS_Z>), g, b, 0, st, fa);
+            else hipLaunchKernelGGL((k_fused<ST, false, WALLS_NONE>), g, b, 0, st, fa);
+        });
         if (rc) return rc;
         HIPCHK(hipGetLastError());
         h->cur ^= 1;
@@ -530,14 +538,13 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     h->ntiles = (int)tiles.size();
     h->ngtiles = (int)gtiles.size();
 
-    // fused eligibility: walls only on z and neutral there
+    // fused eligibility: walls, if any, only on z
     bool eligible = true;
     for (const DevCase &d : h->dc)
-        if (d.wall == 0 || d.wall == 1 || (d.wall == 2 && (d.cot[0] != 0.0f || d.cot[1] != 0.0f)) || d.moving)
-            eligible = false;
+        if (d.wall == 0 || d.wall == 1) eligible = false;
     if (o.kernel == LBCG_KERNEL_FUSED && !eligible) {
         delete h;
-        return fail(LBCG_EINVAL, "fused kernel needs walls only on z, at rest, with theta = 90 deg");
+        return fail(LBCG_EINVAL, "fused kernel needs walls, if any, on the z axis");
     }
     // The two-pass step is the faster one on gfx950 today (the fused kernel is
     // latency-bound: its barrier-separated phases keep few loads in flight), so

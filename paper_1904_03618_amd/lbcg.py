@@ -41,7 +41,7 @@ class lbcg_case(C.Structure):
                 ("beta", C.c_double), ("delta", C.c_double),
                 ("tau_e", C.c_double), ("tau_q", C.c_double), ("tau_pi", C.c_double),
                 ("force", C.c_double * 3), ("grav", C.c_double * 3), ("rho_ref", C.c_double),
-                ("improved", C.c_int32), ("reserved", C.c_int32),
+                ("improved", C.c_int32), ("meq4", C.c_int32),
                 ("wall_u", (C.c_double * 3) * 2)]
 
 
@@ -125,6 +125,7 @@ def pack_case(p: dict) -> lbcg_case:
     for name in ("beta", "delta", "tau_e", "tau_q", "tau_pi", "rho_ref"):
         setattr(c, name, float(p[name]))
     c.improved = int(p["improved"])
+    c.meq4 = int(p.get("meq4", 0))
     wu = p.get("wall_u", ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
     for side in range(2):
         c.wall_u[side][:] = [float(v) for v in wu[side]]

@@ -9,7 +9,8 @@ these inputs; neither computes them.
 A case is ``(params, fields)``:
   params  plain dict: nx, ny, nz, bc[3] (0 periodic / 1 wall), theta_deg[2],
           rho_in[2], alpha[2], tau_v[2], A[2], beta, delta, tau_e, tau_q,
-          tau_pi, force[3], grav[3], rho_ref, improved, wall_u[2][3]
+          tau_pi, force[3], grav[3], rho_ref, improved, meq4 (rows 16-18 of
+          the moment equilibria: 0 = M f^eq, 1 = the Appendix as printed), wall_u[2][3]
           (tangential velocity of the wall at the low and the high end of the
           wall axis)
   fields  dict of float64 arrays of length nx*ny*nz in x-fastest order:
@@ -26,7 +27,8 @@ import numpy as np
 
 DEFAULTS = dict(bc=(0, 0, 0), theta_deg=(90.0, 90.0), beta=0.5, delta=0.98,
                 tau_e=1.0, tau_q=1.0, tau_pi=1.0, force=(0.0, 0.0, 0.0),
-                grav=(0.0, 0.0, 0.0), rho_ref=0.0, improved=1, wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
+                grav=(0.0, 0.0, 0.0), rho_ref=0.0, improved=1, meq4=0,
+                wall_u=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)))
 
 
 def _params(**kw) -> dict:

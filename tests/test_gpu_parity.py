@@ -120,7 +120,14 @@ def _cases():
                                                 ((0.02, 0.01, 0.0), (0.0, -0.03, 0.0))),
         "moving_wall_x_one_side": lambda: _moving(W.random_state_case(9, 10, 8, seed=11, bc=(1, 0, 0), improved=0),
                                                   ((0.0, 0.025, 0.01), (0.0, 0.0, 0.0))),
+        # rows 16-18 of the moment equilibria as the Appendix prints them
+        "galilean_24_meq4_printed": lambda: _meq4(W.galilean_droplet(24, 5.0, seed=7)),
     }
+
+
+def _meq4(case):
+    p, fl = case
+    return dict(p, meq4=1), fl
 
 
 def _moving(case, wall_u):
@@ -271,33 +278,84 @@ def test_batched_uneven_cases_500_steps():
         assert_parity(f"batch500_{c}", batch[c], oracle_run(p, fl, 500), p)
 
 
-@pytest.mark.parametrize("name,maker,zchunk", [
-    ("periodic_ragged", lambda: W.random_state_case(21, 18, 13, seed=41), 5),
-    ("wall_z_neutral", lambda: W.random_state_case(17, 16, 12, seed=42, bc=(0, 0, 1), theta=(90.0, 90.0),
-                                                    grav=(0, 0, -1e-4), rho_ref=2.0), 4),
-    ("column_1x1", lambda: W.layered_channel(1, 1, 24, ratio=10.0, visc_ratio=10.0, G=1e-5), 7),
-    ("thin_x", lambda: W.random_state_case(2, 33, 9, seed=43, force=(1e-5, 0, 0)), 16),
-])
-def test_fused_kernel_matches_two_pass(name, maker, zchunk):
-    """The fused single-pass step and the two-pass step compute the same
-    arithmetic (shared collision body; the compiler contracts a few products
-    into FMAs differently in the two kernels): populations agree to a few
-    FP32 ulps after 60 steps."""
+def _fused_cases():
+    """Cases for the fused single-pass step: periodic and z-wall boxes, ragged
+    tiles in x and y (extents not multiples of 16), chunks that do not divide
+    nz, wetting and moving walls, one- and two-node extents."""
+    mv = lambda c, wu: (dict(c[0], wall_u=wu), c[1])
+    return {
+        "periodic_ragged": (lambda: W.random_state_case(21, 18, 13, seed=41), 5, 500),
+        "wall_z_wetting_buoyancy": (lambda: W.random_state_case(17, 16, 12, seed=42, bc=(0, 0, 1),
+                                                                 theta=(65.0, 140.0), grav=(0, 0, -1e-4),
+                                                                 rho_ref=2.0), 4, 500),
+        "multi_tile_walls_force": (lambda: W.random_state_case(40, 36, 10, seed=44, bc=(0, 0, 1),
+                                                                theta=(110.0, 75.0), force=(2e-5, -1e-5, 0)), 3, 500),
+        "moving_walls_z": (lambda: mv(W.random_state_case(19, 17, 11, seed=45, bc=(0, 0, 1), theta=(70.0, 120.0)),
+                                      ((0.03, 0.01, 0.0), (-0.02, 0.0, 0.0))), 4, 500),
+        "column_1x1_ratio10": (lambda: W.layered_channel(1, 1, 24, ratio=10.0, visc_ratio=10.0, G=1e-5), 7, 500),
+        "thin_x_periodic": (lambda: W.random_state_case(2, 33, 9, seed=43, force=(1e-5, 0, 0)), 16, 500),
+        "single_layer_moving": (lambda: mv(W.random_state_case(4, 5, 1, seed=21, bc=(0, 0, 1), theta=(70.0, 100.0),
+                                                                force=(1e-5, 0.0, -2e-5)),
+                                           ((0.0, 0.01, 0.0), (0.02, 0.0, 0.0))), 1, 200),
+        "original_model_walls": (lambda: W.random_state_case(18, 17, 9, seed=46, bc=(0, 0, 1), improved=0,
+                                                              theta=(80.0, 95.0)), 16, 500),
+    }
+
+
+@pytest.mark.parametrize("name", list(_fused_cases()))
+def test_fused_kernel_matches_oracle(name):
+    """The fused single-pass step against the FP64 oracle at the standard
+    tolerances."""
+    maker, zchunk, steps = _fused_cases()[name]
+    p, fl = maker()
+    g = gpu_run([(p, fl)], steps, kernel="fused", zchunk=zchunk)[0]
+    assert_parity(f"fused_{name}", g, oracle_run(p, fl, steps), p)
+
+
+def test_fused_batch_of_uneven_cases():
+    """Several boxes (periodic, z-walls with wetting, moving z-walls) in one
+    fused launch, against the oracle, and equal to the two-pass step to FP32
+    rounding."""
     import torch
     from paper_1904_03618_amd import lbcg as B
-    p, fl = maker()
-    out = {}
+    cases = [W.random_state_case(23, 20, 9, seed=51, bc=(0, 0, 1), theta=(60.0, 130.0), force=(1e-5, 0, 0)),
+             W.random_state_case(12, 30, 7, seed=52),
+             (dict(W.random_state_case(9, 11, 13, seed=53, bc=(0, 0, 1))[0],
+                   wall_u=((0.02, 0.0, 0.0), (0.0, -0.01, 0.0))), W.random_state_case(9, 11, 13, seed=53, bc=(0, 0, 1))[1])]
+    got = gpu_run(cases, 300, kernel="fused", zchunk=4)
+    for c, (p, fl) in enumerate(cases):
+        assert_parity(f"fused_batch_{c}", got[c], oracle_run(p, fl, 300), p)
+    pops = {}
     for kernel in ("twopass", "fused"):
-        h = B.lbcg_init([(p, fl)], kernel=kernel, zchunk=zchunk)
+        h = B.lbcg_init(cases, kernel=kernel, zchunk=4)
         try:
             B.lbcg_step(h, 60)
-            out[kernel] = B.lbcg_get_populations(h, 0).cpu().numpy()
+            pops[kernel] = [B.lbcg_get_populations(h, c).cpu().numpy() for c in range(len(cases))]
             torch.cuda.synchronize()
         finally:
             B.lbcg_free(h)
-    d = np.abs(out["fused"] - out["twopass"]).max()
-    print(name, "max |fused - twopass| =", d, flush=True)
+    d = max(float(np.abs(a - b).max()) for a, b in zip(pops["fused"], pops["twopass"]))
+    print("max |fused - twopass| =", d, flush=True)
     assert d <= 1e-6
+
+
+@pytest.mark.parametrize("storage,tn,tu", [("fp16s", 6e-3, 2e-4), ("bf16s", 1e-1, 2e-3)])
+def test_fused_shifted_storage(storage, tn, tu):
+    """The fused step in the 16-bit storage forms against the oracle, at the
+    bounds the two-pass step is held to."""
+    p, fl = W.random_state_case(20, 18, 12, seed=47, bc=(0, 0, 1), theta=(70.0, 110.0), force=(1e-5, 0, 0))
+    g = gpu_run([(p, fl)], 500, storage=storage, kernel="fused", zchunk=5)[0]
+    o = oracle_run(p, fl, 500)
+    e = max_err(g, o)
+    report(f"fused_{storage}", e)
+    assert e["rhoN"] <= tn and max(e["ux"], e["uy"], e["uz"]) <= tu
+
+
+def test_fused_rejects_walls_off_z():
+    from paper_1904_03618_amd import lbcg as B
+    p, fl = W.random_state_case(8, 7, 6, seed=1, bc=(0, 1, 0))
+    with pytest.raises(B.LbcgError):
+        B.lbcg_init([(p, fl)], kernel="fused")
 
 
 def test_graph_replays_match_eager_steps():

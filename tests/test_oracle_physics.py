@@ -84,7 +84,7 @@ def test_layered_channel_matches_two_layer_poiseuille():
 def _paper_case(name, improved, steps=30000):
     """The paper's channel cases (Sec. IV.B): a red core |y| <= H/4 between
     blue layers, walls at y = +-H/2, force G along x; E_u as defined there."""
-    rR, rB, aB, M = dict(A=(0.1, 0.8, 0.9, 1 / 8), B=(0.8, 0.1, 0.2, 8.0))[name]
+    rR, rB, aB, M = dict(A=(0.1, 0.8, 0.9, 1 / 8), B=(0.8, 0.1, 0.2, 8.0), C=(0.008, 8.0, 0.9992, 1 / 40))[name]
     aR = 1.0 - (1.0 - aB) * rB / rR
     tmin = 0.6
     tR, tB = (tmin, 0.5 + (tmin - 0.5) / M) if M < 1 else (0.5 + (tmin - 0.5) * M, tmin)
@@ -116,6 +116,23 @@ def test_paper_channel_cases_improved_beats_original():
         e_imp, e_orig = _paper_case(name, 1), _paper_case(name, 0)
         print("case", name, "E_u improved", e_imp, "original", e_orig)
         assert e_imp < imp_max and e_orig > factor * e_imp
+
+
+def test_paper_channel_case_c_ordering():
+    """Sec. IV.B case C (density ratio 1000, viscosity ratio 1/40): the paper
+    prints E_u = 0.36 % (improved) against 6904 % (original).  Here, with the
+    readings of the unstated parameters (less viscous fluid at tau 0.6, halfway
+    walls, beta 0.5), the steady state (1e6 steps, blue kinematic viscosity
+    1.6e-3) gives 12.5 % against 25.9 %: the ordering reproduces, the
+    magnitudes do not (the smeared viscosity jump across the 4-5 node
+    interface dominates the improved model's error at this ratio; the original
+    model's error follows its rho/3 in place of p_k in the third moments,
+    which makes the heavy blue fluid about 800 times too viscous and halts the
+    blue layers).  Checked after 1e5 steps (within 4 % of the converged
+    values)."""
+    e_imp, e_orig = _paper_case("C", 1, steps=100000), _paper_case("C", 0, steps=100000)
+    print("case C E_u improved", e_imp, "original", e_orig)
+    assert e_imp < 0.16 and e_orig > 0.2 and e_orig > 1.5 * e_imp
 
 
 def test_galilean_invariance_improved_not_original():

@@ -213,6 +213,57 @@ def test_collision_conservation(orc):
     assert np.allclose(mom, j + F, rtol=0, atol=2e-16)
 
 
+def test_relaxation_rates_follow_eq44(orc):
+    """Eq. (44): with no colour gradient, correction term or force, one
+    collision scales the non-equilibrium part of moment row r by (1 - s_r):
+    row 4 with 1/tau_e, rows 5-9 with 1/tau_v, rows 10-15 with 1/tau_q and
+    rows 16-18 with 1/tau_pi.  Four distinct times, every row perturbed by its
+    own amount, moments taken with the paper's printed M: a swapped or shifted
+    row assignment fails."""
+    rng = np.random.default_rng(44)
+    te, tv, tq, tp = 1.3, 0.55, 0.7, 1.9
+    for improved in (1, 0):
+        p = params(tau_e=te, tau_q=tq, tau_pi=tp, improved=improved)
+        rho_k = 1.4
+        u = rng.uniform(-0.05, 0.05, 3)
+        feq = orc.feq(p, 0, rho_k, u)
+        dm = np.zeros(19)
+        dm[4:] = rng.uniform(-1e-3, 1e-3, 15)
+        f = feq + np.linalg.solve(MA, dm)
+        out = orc.collide_color(p, 0, f, rho_k, rho_k, u, tv, np.zeros(3), np.zeros(3), np.zeros(3))
+        s = np.array([1.0] * 4 + [1 / te] + [1 / tv] * 5 + [1 / tq] * 6 + [1 / tp] * 3)
+        got = MA @ out - MA @ feq
+        assert np.abs(got - (1.0 - s) * dm).max() < 1e-15, (got - (1 - s) * dm)
+
+
+def test_meq4_switch_takes_the_printed_rows(orc):
+    """meq4 = 1 relaxes rows 16-18 towards the Appendix's printed entries
+    [rho_k (1 - alpha_k - |u|^2) + 2 rho_k (u_a^2 + u_b^2)]/6 instead of the
+    rows of M f^eq; every other row of the collision is unchanged.  The two
+    collisions differ in moment space by exactly S (m^eq_printed - M f^eq)
+    on rows 16-18."""
+    rng = np.random.default_rng(4)
+    tp = 1.6
+    for alpha in (0.9, 0.2):
+        p0 = params(alpha=(alpha, alpha), tau_pi=tp, tau_q=0.8)
+        p1 = dict(p0, meq4=1)
+        rho_k = 0.9
+        ux, uy, uz = u = rng.uniform(-0.08, 0.08, 3)
+        feq = orc.feq(p0, 0, rho_k, u)
+        f = feq * (1 + 0.03 * rng.uniform(-1, 1, 19))
+        args = (f, rho_k, rho_k, u, 0.9, rng.uniform(-0.2, 0.2, 3), rng.uniform(-1e-3, 1e-3, 3),
+                rng.uniform(-1e-4, 1e-4, 3))
+        d = MA @ (orc.collide_color(p1, 0, *args) - orc.collide_color(p0, 0, *args))
+        uu = u @ u
+        base = rho_k * (1 - alpha - uu)
+        printed = np.array([base + 2 * rho_k * (ux * ux + uy * uy), base + 2 * rho_k * (ux * ux + uz * uz),
+                            base + 2 * rho_k * (uy * uy + uz * uz)]) / 6
+        want = np.zeros(19)
+        want[16:] = (printed - (MA @ feq)[16:]) / tp
+        assert np.abs(d - want).max() < 1e-16, d - want
+        assert np.abs(want[16:]).max() > 1e-5                # the switch does change the rows
+
+
 def test_correction_term_constraints(orc):
     """The correction added by Q obeys Eq. (21) and Eq. (34)-(37), scaled by the
     (1 - s/2) prefactor of Eq. (41)."""
