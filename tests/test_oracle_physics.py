@@ -159,6 +159,67 @@ def test_galilean_invariance_improved_not_original():
     assert abs(out[0][0] - u0 * T) > 1.5 and out[0][1] > 0.5
 
 
+def _circle_fit(x, z):
+    """Algebraic least-squares circle through points (centre x, centre z, radius)."""
+    A = np.stack([x, z, np.ones_like(x)], 1)
+    c = np.linalg.lstsq(A, x * x + z * z, rcond=None)[0]
+    xc, zc = c[0] / 2, c[1] / 2
+    return xc, zc, np.sqrt(c[2] + xc * xc + zc * zc)
+
+
+def _zero_crossings(rn, zmin):
+    """Linearly interpolated rho^N = 0 crossings along rows (periodic x) and
+    columns of a 2D field rn[z, x], from row zmin up."""
+    nz, nx = rn.shape
+    pts = []
+    for z in range(zmin, nz):
+        a, b = rn[z], np.roll(rn[z], -1)
+        for x in np.nonzero(a * b < 0)[0]:
+            pts.append((x + a[x] / (a[x] - b[x]), z))
+    for z in range(zmin, nz - 1):
+        a, b = rn[z], rn[z + 1]
+        for x in np.nonzero(a * b < 0)[0]:
+            pts.append((x, z + a[x] / (a[x] - b[x])))
+    return np.array(pts, dtype=float)
+
+
+def _sessile_angle(theta, nx=64, nz=32, R0=12.0, steps=6000):
+    """A quasi-2D drop (ny = 1) on the bottom wall (halfway at z = -1/2),
+    started as the circular cap of the requested angle with area pi R0^2 / 2,
+    run for `steps` steps; the contact angle through the drop from a circle
+    fitted to the rho^N = 0 contour three layers and more above the wall:
+    cos(theta) = -(z_c + 1/2) / R."""
+    p = dict(W.DEFAULTS)
+    p.update(nx=nx, ny=1, nz=nz, bc=(0, 0, 1), theta_deg=(theta, 90.0), rho_in=(1.0, 1.0),
+             alpha=(1 / 3, 1 / 3), tau_v=(1.0, 1.0), A=(0.01, 0.01))
+    th = np.radians(theta)
+    R = np.sqrt(0.5 * np.pi * R0 * R0 / (th - np.sin(th) * np.cos(th)))   # segment area R^2 (th - sin th cos th)
+    n = nx * nz
+    x, z = np.arange(n) % nx, np.arange(n) // nx
+    inside = (x - nx / 2 + 0.5) ** 2 + (z + 0.5 + R * np.cos(th)) ** 2 <= R * R
+    o = _run(p, dict(rhoR=np.where(inside, 1.0, 0.0), rhoB=np.where(inside, 0.0, 1.0), ux=np.zeros(n),
+                     uy=np.zeros(n), uz=np.zeros(n)), steps)
+    pts = _zero_crossings(o["rhoN"].reshape(nz, nx), 3)
+    xc, zc, Rf = _circle_fit(pts[:, 0], pts[:, 1])
+    return float(np.degrees(np.arccos(np.clip(-(zc + 0.5) / Rf, -1.0, 1.0))))
+
+
+def test_sessile_drop_contact_angle():
+    """The wetting reading (geometric ghost layer: the phase field changes by
+    cot(theta) |grad_par rho^N| across the half link, theta through red; the
+    paper states only theta ~ 90 deg for Sec. IV.D) holds a resting drop at the
+    requested angle: measured 61.6, 89.7 and 134.0 deg after 6000 steps (135.2
+    after 12000) for 60, 90 and 135 deg.  The circle fit itself is checked on
+    the start state.  At 150 deg this reading does not hold a cap: the drop
+    keeps receding (146 deg after 2000 steps, 171 after 12000)."""
+    for theta in (60.0, 90.0, 135.0):
+        got = _sessile_angle(theta)
+        print("sessile drop: requested", theta, "measured", got)
+        assert abs(got - theta) < 3.0, (theta, got)
+    # the measurement recovers the angle of the sharp start cap itself
+    assert abs(_sessile_angle(60.0, steps=0) - 60.0) < 3.0
+
+
 def test_shear_wave_decay_gives_the_viscosity():
     """Single phase (alpha = 1/3, one colour): a sinusoidal shear wave
     u_x = U sin(k z) decays as exp(-nu k^2 t) with nu = c_s^2 (tau_v - 1/2),
