@@ -1,12 +1,17 @@
 #!/usr/bin/env python
 """Throughput of the improved 3D colour-gradient LB step on one MI355X.
 
-Workload: the Galilean droplet, a 128^3 periodic D3Q19 lattice, density and
-viscosity ratio 1, droplet radius 20 at a seeded random centre, uniform
-initial velocity (0.05, 0.05, 0.05), tau_v drawn in [0.6, 1.0] from the seed,
-plain FP32 populations.  A step is one full time step of the method (moments,
-colour gradient, MRT collision with correction term and perturbation,
-recoloring, streaming).  Prints one JSON line.
+Headline workload: the 3D Rayleigh-Taylor instability (Sec. IV.C) on a
+128 x 128 x 512 D3Q19 lattice, walls on z, periodic sides, Atwood number 0.5
+(rho^in 3/1), gravity 2e-5, Re = 1024, single-mode perturbation of amplitude
+0.05 L, plain FP32 populations; the largest single-GPU configuration of the
+benchmark set.  A step is one full time step of the method (moments, colour
+gradient, MRT collision with correction term and perturbation, recoloring,
+streaming with bounce-back walls).  Beside it: the same case scaled to
+256 x 256 x 1024, the 16-bit storage forms, the 128^3 Galilean droplet, the
+batch of 256 droplet-impact boxes (launch shape tuned on the spot), the
+learned surrogate, a copy probe and the FP64 oracle on the host cores.
+Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -24,18 +29,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + HBM GB/s (% peak): FP32 plain vs FP16-store/surrogate at stated error"
 HBM_PEAK_GBPS = 8000.0
-# Algorithmic HBM bytes per node of one launch of the collision pass: read 38
-# population deviations and the writers' stored (rho_R, rho_B) (8 B per node),
-# read the node's aux value (rho^N, Qbar: 16 B), write 38 deviations and the
-# node's (rho_R, rho_B).
 POP = {"fp32": 4, "fp16s": 2, "bf16s": 2}
-COLLIDE_BYTES = {k: 38 * b + 8 + 16 + 38 * b + 8 for k, b in POP.items()}
-# The fused single-pass step: populations and stored densities read and
-# written once (the phase-field halo lives in LDS).
+# Algorithmic HBM bytes per fluid node and step of the method: 38
+# populations read and 38 written (the figure the roofline is priced at).
+ALGO_BYTES = {k: 2 * 38 * b for k, b in POP.items()}
+# What the fused step moves by design: the populations plus the colour
+# densities each writer stores with its values (8 B read, 8 B written).
 FUSED_BYTES = {k: 2 * (38 * b + 8) for k, b in POP.items()}
-# The method's own minimum per node and step in this storage: populations and
-# stored densities read and written once.
-STEP_BYTES = {k: 2 * (38 * b + 8) for k, b in POP.items()}
+# The two-pass step: populations and stored densities read twice (moments
+# pass, collision pass), the aux value written once and read once.
+TWOPASS_BYTES = {k: 3 * (38 * b + 8) + 2 * 16 for k, b in POP.items()}
+KERNEL_INDEX = {"aux": "k_aux", "ghost": "k_ghost", "collide": "k_collide", "fused": "k_fused"}
 
 
 def kernel_source_hash():
@@ -46,63 +50,73 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage, kernel):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, only if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_galilean128_traffic.json")
+def measured_traffic(kernel, storage, workload):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, only if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{storage}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         d = json.load(fh)
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return {"bytes_per_launch": d["bytes_per_launch"], "bytes_per_node": d["bytes_per_node"],
+            "file": os.path.relpath(path, ROOT)}
 
 
-def dominant(kt, storage):
-    """(name, avg ms, algorithmic bytes per node) of the kernel that dominates a step."""
-    if kt["fused"][1]:
-        return "k_fused", kt["fused"][0] / kt["fused"][1], FUSED_BYTES[storage]
-    return "k_collide", kt["collide"][0] / kt["collide"][1], COLLIDE_BYTES[storage]
-
-
-def run_form(B, cases, storage, steps, warmup, timing=True, kernel="auto", kernel_steps=200, repeats=0,
-             repeat_steps=200):
-    """Time `steps` steps (no per-kernel events inside the timed region), then,
-    if timing, `kernel_steps` more steps with HIP event pairs around every
-    kernel for the per-kernel averages.  Fields are taken after the timed
-    steps.  With repeats > 0, also time that many further runs of
-    repeat_steps steps each (ms per step of each run, returned as kt["repeats"])."""
+def timed_run(B, cases, storage, steps, warmup, kernel_steps=100, repeats=0, repeat_steps=200, **opts):
+    """Time `steps` steps with HIP events on the handle's stream (no
+    per-kernel events inside), then `repeats` further runs, then
+    `kernel_steps` steps with event pairs around every kernel.  Returns
+    (ms per step, per-kernel average ms, repeat ms list, fields of case 0
+    after the timed steps, the options the handle reports)."""
     import torch
-    s = B.Solver(cases, storage=storage, kernel=kernel)
+    s = B.Solver(cases, storage=storage, **opts)
     try:
+        stream = torch.cuda.current_stream()
         s.step(warmup)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        e0.record()
+        e0.record(stream)
         s.step(steps)
-        e1.record()
+        e1.record(stream)
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
+        ms = e0.elapsed_time(e1) / steps
         fl = {k: v.double() for k, v in s.fields(0).items() if k != "diag"}
         reps = []
         for _ in range(repeats):
-            e0.record()
+            e0.record(stream)
             s.step(repeat_steps)
-            e1.record()
+            e1.record(stream)
             torch.cuda.synchronize()
             reps.append(e0.elapsed_time(e1) / repeat_steps)
-        kt = None
-        if timing:
+        kt = {}
+        if kernel_steps and not opts.get("graph_steps"):
             B.lbcg_timing(s.h, 1)
             B.lbcg_timing_read(s.h)
             s.step(kernel_steps)
-            kt = B.lbcg_timing_read(s.h)
-            kt["repeats"] = reps
-        return ms, kt, fl
+            raw = B.lbcg_timing_read(s.h)
+            kt = {KERNEL_INDEX[k]: v[0] / v[1] for k, v in raw.items() if v[1]}
+        return ms, kt, reps, fl
     finally:
         s.close()
+
+
+def roofline(kernels, storage, N, ms_step, twopass):
+    """Roofline of the dominant kernel (the fused step, or the two-pass
+    collision pass) at the method's algorithmic bytes, and the step's."""
+    if "k_fused" in kernels:
+        name, kms, design = "k_fused", kernels["k_fused"], FUSED_BYTES[storage]
+    else:
+        name, kms, design = "k_collide", kernels.get("k_collide", ms_step), TWOPASS_BYTES[storage]
+    ach = ALGO_BYTES[storage] * N / (kms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
+            "kernel": f"{name}<{storage}>", "kernel_avg_ms": kms, "bytes_per_node": ALGO_BYTES[storage],
+            "design_bytes_per_node": design if name == "k_fused" else None,
+            "design_GBps": design * N / (kms * 1e-3) / 1e9 if name == "k_fused" else None,
+            "step_achieved": ALGO_BYTES[storage] * N / (ms_step * 1e-3) / 1e9,
+            "step_frac": ALGO_BYTES[storage] * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS}
 
 
 def copy_probe(mib):
@@ -131,7 +145,8 @@ def copy_probe(mib):
 def batch_bench(B, steps, warmup, storage="fp16s", ncases=256):
     """Batched droplet impact: `ncases` independent boxes of side 48..128 in one
     handle (one launch per kernel over every box), FP16S storage, launch shape
-    picked by the autotuner.  Aggregate MLUPS over all boxes."""
+    picked by the autotuner on this machine (timed now, not read from a cache).
+    Aggregate MLUPS over all boxes and the step's roofline."""
     import torch
     from paper_1904_03618_amd import autotune as AT
     from paper_1904_03618_amd import workloads as W
@@ -139,7 +154,9 @@ def batch_bench(B, steps, warmup, storage="fp16s", ncases=256):
     cases = W.impact_batch(ncases)
     gen_s = time.time() - t0
     N = sum(p["nx"] * p["ny"] * p["nz"] for p, _ in cases)
-    opts, rep = AT.autotune(cases, storage)
+    t0 = time.time()
+    opts, rep = AT.autotune(cases, storage, cache=None, retune=True)
+    tune_s = time.time() - t0
     s = B.Solver(cases, storage=storage, diag_every=0, **opts)
     try:
         s.step(warmup)
@@ -154,15 +171,31 @@ def batch_bench(B, steps, warmup, storage="fp16s", ncases=256):
         bad = sum(1 for c in range(ncases) if not np.isfinite(B.lbcg_moments(s.h, c)).all())
     finally:
         s.close()
+    ach = ALGO_BYTES[storage] * N / (ms * 1e-3) / 1e9
+    trials = [{"options": t["options"], "MLUPS_sample": t["MLUPS"]} for t in rep.get("trials", [])]
     return {"workload": f"{ncases} droplet-impact boxes, sides 48..128 (seeded), wetting bottom wall",
             "storage": storage, "nodes": N, "MLUPS": N / ms / 1e3, "ms_per_step": ms, "steps": steps,
-            "warmup": warmup, "options": opts, "autotune_key": rep["key"], "autotune_cached": rep["cached"],
+            "warmup": warmup, "options": opts, "autotune": {"key": rep["key"], "cached": rep["cached"],
+                                                             "tuned_here_s": tune_s, "trials": trials},
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBPS, "level": "step", "bytes_per_node": ALGO_BYTES[storage]},
             "cases_non_finite": bad, "input_generation_s": gen_s}
 
 
-def cpu_baseline(p, fl, budget_s):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(p, fl, budget_s, label):
     """The FP64 oracle on the host cores, on a bounded sample of the same
-    workload (the full 128^3 lattice for a few steps)."""
+    workload: the full lattice for as many steps as fit the budget."""
     from oracle import oracle as O
     f = O.init(p, fl["rhoR"], fl["rhoB"], fl["ux"], fl["uy"], fl["uz"])
     N = p["nx"] * p["ny"] * p["nz"]
@@ -173,33 +206,10 @@ def cpu_baseline(p, fl, budget_s):
     t = time.time()
     O.run(p, f, n)
     dt = time.time() - t
-    out = {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
-           "sample": f"galilean droplet 128^3, FP64 oracle, {n} timed steps after 1 untimed "
-                     f"({dt:.1f} s)"}
-    out["one_core"] = cpu_one_core()
-    return out
-
-
-def cpu_one_core():
-    """The same oracle on one core (one step of the full lattice), in a child
-    process started with OMP_NUM_THREADS=1 (the thread count is fixed when
-    OpenMP starts); the child never touches the GPU."""
-    import subprocess
-    code = ("import json, sys, time\n"
-            f"sys.path.insert(0, {ROOT!r})\n"
-            "from oracle import oracle as O\n"
-            "from paper_1904_03618_amd import workloads as W\n"
-            "p, fl = W.galilean_droplet(128, 20.0, seed=1904)\n"
-            "f = O.init(p, fl['rhoR'], fl['rhoB'], fl['ux'], fl['uy'], fl['uz'])\n"
-            "t = time.time(); O.run(p, f, 1); dt = time.time() - t\n"
-            "print(json.dumps({'value': 128 ** 3 / dt / 1e6, 'unit': 'MLUPS', 'cores': O.threads(),\n"
-            "                  'sample': f'one step of the full lattice ({dt:.1f} s)'}))\n")
-    env = dict(os.environ, OMP_NUM_THREADS="1")
-    try:
-        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=600)
-        return json.loads(r.stdout.strip().splitlines()[-1])
-    except (subprocess.SubprocessError, ValueError, IndexError) as e:
-        return {"error": str(e)[:200]}
+    del f
+    return {"value": N * n / dt / 1e6, "unit": "MLUPS", "cores": O.threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+            "sample": f"{label}, FP64 oracle, {n} timed steps of the full lattice after 1 untimed ({dt:.1f} s)"}
 
 
 MFMA_BF16_PEAK_TFLOPS = 2500.0
@@ -209,9 +219,7 @@ def surrogate_bench(with_rt):
     """The learned surrogate (BF16 MFMA U-Net): full-domain inference on the
     128 x 128 x 512 Rayleigh-Taylor box and a training step on four 64^3
     crops, against the dense BF16 matrix-core peak; optionally the gated
-    hybrid on a 32 x 32 x 128 Rayleigh-Taylor run (train, then jump 100 steps
-    at a time while the bubble and spike fronts stay within 1 lattice unit of
-    the LB run) with its time-to-solution gain over plain LB."""
+    hybrid on a Rayleigh-Taylor run with its time-to-solution against plain LB."""
     from paper_1904_03618_amd import surrogate as S
     inf = S.bench_unet((1, 512, 128, 128), iters=5, train=False)
     tr = S.bench_unet((4, 64, 64, 64), iters=5, train=True)
@@ -225,34 +233,26 @@ def surrogate_bench(with_rt):
     }
     if with_rt:
         from paper_1904_03618_amd import surrogate_rt as R
-        rt = R.experiment(L=32, gates=(1.0,))
-        g = rt["gates"]["1.0"]
-        res["rt_hybrid"] = {
-            "lattice": rt["lattice"], "jump_steps": rt["every"], "heal_steps": rt["heal"], "steps": rt["steps"],
-            "train_amps": rt["train_amps"], "val_amp": rt["val_amp"], "eval_amp": rt["eval_amp"],
-            "train_iters": rt["train_iters"], "seeds": rt["seeds"], "selected_seed": rt["selected_seed"],
-            "selected_after": rt["selected_after"], "validation": rt["validation"],
-            "train_s": rt["train_s"], "loss_first": rt["loss_first"],
-            "loss_last": rt["loss_last"], "gate_lu": 1.0, "accepted": g["accepted"], "jumps": g["jumps"],
-            "max_accepted_front_error": g["max_accepted_error"], "final_front_error": g["final_front_error"],
-            "lb_s": rt["lb_s"], "hybrid_s": g["hybrid_s"], "gain": g["gain"],
-            "persistence": g["persistence"]}
+        res["rt_hybrid"] = R.bench_summary(R.experiment(L=32, gates=(1.0,)))
     return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--forms", default="fp16s,bf16s", help="extra storage forms to time ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel", default="auto", choices=["auto", "twopass", "fused"])
+    ap.add_argument("--large", type=int, default=1, help="also time the 256 x 256 x 1024 box (0: skip)")
+    ap.add_argument("--galilean", type=int, default=1, help="also time the 128^3 Galilean droplet (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100, help="timed steps of the impact batch (0: skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--repeats", type=int, default=5, help="further 200-step runs of the headline case")
     ap.add_argument("--surrogate", type=int, default=1, help="time the surrogate network (1) or skip it (0)")
     ap.add_argument("--surrogate-rt", type=int, default=1,
-                    help="run the gated surrogate/LB hybrid on a 32x32x128 Rayleigh-Taylor case (0: skip)")
+                    help="run the gated surrogate/LB hybrid on a Rayleigh-Taylor case (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=1024,
                     help="size of the device copy that measures the attainable HBM rate (0: skip)")
     args = ap.parse_args()
@@ -267,29 +267,49 @@ def main():
     from paper_1904_03618_amd import workloads as W
 
     torch.cuda.set_device(0)
-    p, fl = W.galilean_droplet(128, 20.0, seed=1904)
+    label = "rayleigh-taylor 128x128x512"
+    p, fl = W.rayleigh_taylor(128)
     N = p["nx"] * p["ny"] * p["nz"]
     cases = [(p, fl)]
 
-    ms, kt, ref = run_form(B, cases, "fp32", args.steps, args.warmup, kernel=args.kernel, repeats=5)
-    reps = kt.pop("repeats")
-    ms_step = ms / args.steps
-    mlups = N * args.steps / (ms * 1e-3) / 1e6
-    kname, avg_col, kbytes = dominant(kt, "fp32")
-    ach = kbytes * N / (avg_col * 1e-3) / 1e9
-    traffic = measured_traffic("fp32", kname)
+    ms, kt, reps, ref = timed_run(B, cases, "fp32", args.steps, args.warmup, repeats=args.repeats, kernel=args.kernel)
+    mlups = N / (ms * 1e-3) / 1e6
+    roof = roofline(kt, "fp32", N, ms, args.kernel == "twopass")
+    roof["traffic"] = measured_traffic(roof["kernel"].split("<")[0], "fp32", "rt128x128x512")
 
     forms = {}
     for st in [s for s in args.forms.split(",") if s]:
-        fms, fkt, ff = run_form(B, cases, st, args.steps, args.warmup, kernel=args.kernel)
-        fname, f_avg, f_bytes = dominant(fkt, st)
+        fms, fkt, _, ff = timed_run(B, cases, st, args.steps, args.warmup, kernel=args.kernel)
         err_n = float((ff["rhoN"] - ref["rhoN"]).abs().max())
         err_u = float(max((ff[k] - ref[k]).abs().max() for k in ("ux", "uy", "uz")))
-        forms[st] = {"MLUPS": N * args.steps / (fms * 1e-3) / 1e6, "ms_per_step": fms / args.steps,
-                     "kernel": fname, "kernel_avg_ms": f_avg,
-                     "kernel_GBps": f_bytes * N / (f_avg * 1e-3) / 1e9,
+        froof = roofline(fkt, st, N, fms, args.kernel == "twopass")
+        froof["traffic"] = measured_traffic(froof["kernel"].split("<")[0], st, "rt128x128x512")
+        forms[st] = {"MLUPS": N / (fms * 1e-3) / 1e6, "ms_per_step": fms, "kernels_avg_ms": fkt,
+                     "roofline": froof, "vs_fp32": N / (fms * 1e-3) / 1e6 / mlups,
                      "max_abs_diff_vs_fp32_after_steps": {"rhoN": err_n, "u": err_u,
                                                           "steps": args.steps + args.warmup}}
+
+    extra = {}
+    if args.large:
+        pl, fll = W.rayleigh_taylor(256)
+        NL = pl["nx"] * pl["ny"] * pl["nz"]
+        big = {}
+        for st in ("fp32", "fp16s"):
+            lms, lkt, _, _ = timed_run(B, [(pl, fll)], st, min(args.steps, 100), 5, kernel_steps=20,
+                                       kernel=args.kernel)
+            big[st] = {"MLUPS": NL / (lms * 1e-3) / 1e6, "ms_per_step": lms, "kernels_avg_ms": lkt,
+                       "roofline": roofline(lkt, st, NL, lms, args.kernel == "twopass")}
+        del fll
+        extra["rayleigh_taylor_256x256x1024"] = big
+    if args.galilean:
+        pg, flg = W.galilean_droplet(128, 20.0, seed=1904)
+        NG = 128 ** 3
+        gal = {}
+        for st in ("fp32", "fp16s"):
+            gms, gkt, _, _ = timed_run(B, [(pg, flg)], st, args.steps, args.warmup, kernel=args.kernel)
+            gal[st] = {"MLUPS": NG / (gms * 1e-3) / 1e6, "ms_per_step": gms, "kernels_avg_ms": gkt,
+                       "roofline": roofline(gkt, st, NG, gms, args.kernel == "twopass")}
+        extra["galilean_droplet_128"] = gal
 
     copy = copy_probe(args.copy_probe_mib) if args.copy_probe_mib > 0 else None
     sur = surrogate_bench(args.surrogate_rt) if args.surrogate else None
@@ -297,29 +317,28 @@ def main():
 
     out = {
         "metric": METRIC, "value": mlups, "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "galilean droplet 128^3 (periodic, R=20, u0=0.05, seed 1904)",
-                   "lattice": [128, 128, 128], "storage": "fp32", "tau_v": p["tau_v"][0],
-                   "parallelism": "single GPU"},
-        "step_algorithmic_GBps": mlups * 1e6 * STEP_BYTES["fp32"] / 1e9,
+        "config": {"workload": "rayleigh-taylor 128x128x512 (walls on z, At 0.5, g 2e-5, Re 1024, amplitude 0.05 L)",
+                   "lattice": [128, 128, 512], "storage": "fp32", "kernel": args.kernel,
+                   "tau_v": list(p["tau_v"]), "parallelism": "single GPU"},
         "repeat_runs": {"runs": len(reps), "steps": 200, "ms_per_step": reps,
-                        "median_MLUPS": N / (float(np.median(reps)) * 1e-3) / 1e6},
-        "kernels_avg_ms": {k: v[0] / v[1] for k, v in kt.items() if v[1]},
-        "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBPS, "kernel": kname + "<fp32>",
-                     "bytes_per_node": kbytes, "traffic": traffic},
+                        "median_MLUPS": N / (float(np.median(reps)) * 1e-3) / 1e6 if reps else None},
+        "kernels_avg_ms": kt,
+        "roofline": roof,
         "forms": forms,
     }
+    out.update(extra)
     if batch:
         out["batch"] = batch
     if sur:
         out["surrogate"] = sur
     if copy:
         out["copy_probe"] = copy
-        out["roofline"]["frac_of_copy_probe"] = ach / copy["GBps"]
+        out["roofline"]["frac_of_copy_probe_design_bytes"] = (roof["design_GBps"] / copy["GBps"]
+                                                              if roof.get("design_GBps") else None)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, fl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, fl, args.cpu_seconds, label)
     print(json.dumps(out), flush=True)
 
 

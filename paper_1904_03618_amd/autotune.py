@@ -4,16 +4,18 @@ For a list of cases and a storage format it times each candidate launch
 configuration (step kernel, workgroup tile, persistent grid, z-chunk, graph
 capture) on a scratch handle built from a sample of the cases, and returns the
 fastest as keyword options for ``lbcg_init``.  Results are cached in a JSON
-file keyed by the box-size class of the cases and the storage format, so a
-later run with the same kind of workload reuses the choice without timing.
+file in the user's cache directory (``LBCG_AUTOTUNE_CACHE`` overrides it),
+keyed by the box-size class of the cases and the storage format, so a later
+run on the same machine with the same kind of workload reuses the choice
+without timing; ``cache=None`` times every call.
 """
 from __future__ import annotations
 
 import json
 import os
 
-PKG = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_CACHE = os.environ.get("LBCG_AUTOTUNE_CACHE", os.path.join(PKG, "autotune_cache.json"))
+DEFAULT_CACHE = os.environ.get("LBCG_AUTOTUNE_CACHE",
+                               os.path.join(os.path.expanduser("~"), ".cache", "lbcg", "autotune.json"))
 
 
 def _moving(p):
@@ -35,26 +37,27 @@ def box_class(cases, storage):
 
 
 def candidates(eligible_fused):
+    """Launch shapes to time: the two-pass step (256- or 128-node tiles,
+    with or without a persistent grid) and, where the cases allow it, the
+    fused step at 16-, 32- and 64-plane chunks; each with and without an
+    8-step graph."""
     out = []
     for block in (256, 128):
-        for persistent in (0, 1024, 2048):
+        for persistent in (0, 1024):
             for graph in (0, 8):
                 out.append(dict(kernel="twopass", block_nodes=block, persistent_blocks=persistent,
                                 graph_steps=graph))
     if eligible_fused:
-        for zc in (16, 32):
-            out.append(dict(kernel="fused", zchunk=zc, persistent_blocks=0, graph_steps=0))
+        for zc in (16, 32, 64):
+            for graph in (0, 8):
+                out.append(dict(kernel="fused", zchunk=zc, persistent_blocks=0, graph_steps=graph))
     return out
 
 
 def _fused_ok(cases):
-    """The fused kernel takes walls only on z, neutral (90 deg) and at rest."""
-    for p, _ in cases:
-        if p["bc"][0] or p["bc"][1] or _moving(p):
-            return False
-        if p["bc"][2] and any(abs(t - 90.0) > 0 for t in p["theta_deg"]):
-            return False
-    return True
+    """The fused kernel takes boxes without walls or with walls on z (any
+    contact angle, at rest or moving)."""
+    return all(not (p["bc"][0] or p["bc"][1]) for p, _ in cases)
 
 
 def time_config(B, cases, storage, opts, steps=24, warmup=8):
@@ -97,6 +100,7 @@ def autotune(cases, storage="fp16s", sample_every=8, steps=24, warmup=8, cache=D
     best = min(results, key=lambda r: r["ms_per_step"])
     table[key] = {"options": best["options"], "sample_nodes": nodes, "trials": results}
     if cache:
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
         tmp = cache + ".tmp"
         with open(tmp, "w") as fh:
             json.dump(table, fh, indent=1)

@@ -300,13 +300,12 @@ __device__ inline void pull_decode(const StepArgs &a, DC &C, const Coord &c, con
     }
 }
 
-template <int ST, bool MV, int CPP>
-__device__ inline void pull_node_rl(const StepArgs &a, DC &C, const Coord &c, const float2 *const (&rl)[3], int ri,
-                                    NodeState &s)
+// The node state from the loaded populations of node c (ri: its index in
+// the density planes).
+template <int ST, bool MV>
+__device__ inline void pull_finish(const StepArgs &a, DC &C, const Coord &c, const float2 *const (&rl)[3], int ri,
+                                   const typename Storage<ST>::P (&v)[Q], NodeState &s)
 {
-    typename Storage<ST>::P v[Q];
-    pull_issue<ST, CPP>(a, C, c, v);
-    __builtin_amdgcn_sched_barrier(0);       // every load issued before the first use
     const float2 own = rl[1][ri];
     float eR = 0.f, eB = 0.f;
     s.jx = s.jy = s.jz = 0.f;
@@ -489,7 +488,7 @@ __device__ inline float tau_v(DC &C, float rn)
 // correction term, body force and perturbation (Eq. 41-45, 53), recoloring
 // (Eq. 10-11) and the store of both colours' deviations at the node's own
 // slots.  st: colour gradient and Q_alpha (Eq. 49); rn: the node's rho^N.
-template <int ST>
+template <int ST, int CPS = CP_DEFAULT>
 __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const NodeState &s,
                                     const Stencil &st, float rn)
 {
@@ -669,11 +668,9 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
         const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
         const float db = fs[i] - dr;
         const uint32_t off = (uint32_t)node * (uint32_t)sizeof(P);
-        buf_st<P, CP_DEFAULT>(rsrc(outb + (size_t)i * NS, NS * sizeof(P)), off,
-                              P{S::enc(dr, a.scale), S::enc(db, a.scale)});
+        buf_st<P, CPS>(rsrc(outb + (size_t)i * NS, NS * sizeof(P)), off, P{S::enc(dr, a.scale), S::enc(db, a.scale)});
     }
-    buf_st<float2, CP_DEFAULT>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u,
-                               make_float2(RR, RB));
+    buf_st<float2, CPS>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u, make_float2(RR, RB));
 }
 
 // ------------------------------------------------------------- k_collide
@@ -781,58 +778,112 @@ __device__ inline void fused_stage_store(float2 (*rring)[RREG], int zl, const Rh
         if (r.d[k] >= 0) dst[r.d[k]] = r.v[k];
 }
 
-// Pull node (x, y, zp) of the case (coordinates wrapped into the box; rx, ry
-// its position relative to the tile origin, zl its logical plane).
-template <int ST, bool MV, int WL>
-__device__ inline void fused_pull(const StepArgs &a, DC &C, float2 (*rring)[RREG], int x, int y, int zp, int rx,
-                                  int ry, int zl, NodeState &s)
+// Position (relative to the tile origin) of entry e of the halo of width h
+// around an ax x ay tile: the 2h rows below and above (w = ax + 2h wide,
+// nrow entries), then the 2h columns beside the tile.
+__device__ inline void halo_pos(int e, int w, int nrow, int h, int ax, int ay, int &rx, int &ry)
 {
-    const Coord c = make_coord_xyz<WL>(C, x, y, zp);
-    const float2 *const rl[3] = {rring[rslot(zl - 1)], rring[rslot(zl)], rring[rslot(zl + 1)]};
-    pull_node_rl<ST, MV, CP_DEFAULT>(a, C, c, rl, ridx(rx, ry), s);
+    if (e < nrow) {
+        const int r = e / w;
+        rx = e - r * w - h;
+        ry = r < h ? r - h : ay + (r - h);
+    } else {
+        const int e1 = e - nrow, cc = e1 / ay;
+        ry = e1 - cc * ay;
+        rx = cc < h ? cc - h : ax + (cc - h);
+    }
 }
 
 // Aux values of plane zp (0 <= zp < nz) into the ring slot of plane zl (zl =
 // zp, or zp -+ nz for the periodic neighbours of the chunk's end planes): the
-// lane's own node (pulled state kept in s), then the halo of width h (1, or 2
-// on a wall layer) pulled by the lanes of two consecutive waves, rotated by
-// plane.  On a wall layer of a case with moving walls the density factor qs
-// of Qbar goes to wq[side] for the ghost layer.
+// lane's own node (pulled state kept in s) and the halo of width h (1, or 2
+// on a wall layer).  The halo holds at most 144 nodes, so a lane pulls at
+// most one halo node; the halo duty falls on consecutive waves, rotated by
+// plane.  Lanes outside a ragged tile (and past the halo)
+// pull a valid node and drop the result.  On a wall layer of a case with
+// moving walls the density factor qs of Qbar goes to wq[side] for the ghost
+// layer.
 template <int ST, bool MV, int WL>
 __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], float2 (*rring)[RREG],
                                    float (*wq)[FREG], int zl, int zp, int x0, int y0, int ax, int ay, int h,
                                    bool active, int tx, int ty, NodeState &s)
 {
+    using P = typename Storage<ST>::P;
     float4 *slot = ring[fslot(zl)];
     const bool wlo = MV && C.wall == 2 && zp == 0, whi = MV && C.wall == 2 && zp == C.nz - 1;
-    float qs;
-    if (active) {
-        fused_pull<ST, MV, WL>(a, C, rring, x0 + tx, y0 + ty, zp, tx, ty, zl, s);
-        slot[fidx(tx, ty)] = aux_value(C, s, qs);
-        if (wlo) wq[0][fidx(tx, ty)] = qs;
-        if (whi) wq[1][fidx(tx, ty)] = qs;
-    }
+    const float2 *const rl[3] = {rring[rslot(zl - 1)], rring[rslot(zl)], rring[rslot(zl + 1)]};
     const int w = ax + 2 * h, nrow = 2 * h * w, nh = nrow + 2 * h * ay;
-    const int e0 = ((int)threadIdx.x - 64 * (zl & 3) + 256) & 255;   // halo duty rotates over the waves
-    for (int e = e0; e < nh; e += 256) {
-        int rx, ry;
-        if (e < nrow) {
-            const int r = e / w;
-            rx = e - r * w - h;
-            ry = r < h ? r - h : ay + (r - h);
+    const int rot = zl & 3;
+    const int e = ((int)threadIdx.x - 64 * rot + 256) & 255;
+    const int wave = (int)threadIdx.x >> 6;
+    const bool wave_halo = __builtin_amdgcn_readfirstlane((((wave - rot) & 3) * 64 < nh) ? 1 : 0) != 0;
+    if constexpr (sizeof(P) == 8) {
+        // FP32: a wave with halo duty issues both nodes' loads before it waits
+        // (one memory latency instead of two, at 2 waves per SIMD)
+        const int ox = min(tx, ax - 1), oy = min(ty, ay - 1);
+        const Coord co = make_coord_xyz<WL>(C, x0 + ox, y0 + oy, zp);
+        P vo[Q];
+        pull_issue<ST, CP_DEFAULT>(a, C, co, vo);
+        float qs;
+        if (wave_halo) {
+            const int eh = min(e, nh - 1);
+            int rx, ry;
+            halo_pos(eh, w, nrow, h, ax, ay, rx, ry);
+            const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
+            const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
+            P vh[Q];
+            pull_issue<ST, CP_DEFAULT>(a, C, ch, vh);
+            __builtin_amdgcn_sched_barrier(0);   // both nodes' loads issued before the first use
+            pull_finish<ST, MV>(a, C, co, rl, ridx(ox, oy), vo, s);
+            if (active) {
+                slot[fidx(tx, ty)] = aux_value(C, s, qs);
+                if (wlo) wq[0][fidx(tx, ty)] = qs;
+                if (whi) wq[1][fidx(tx, ty)] = qs;
+            }
+            NodeState hs;
+            pull_finish<ST, MV>(a, C, ch, rl, ridx(rx, ry), vh, hs);
+            if (e < nh) {
+                slot[fidx(rx, ry)] = aux_value(C, hs, qs);
+                if (wlo) wq[0][fidx(rx, ry)] = qs;
+                if (whi) wq[1][fidx(rx, ry)] = qs;
+            }
         } else {
-            const int e1 = e - nrow, cc = e1 / ay;
-            ry = e1 - cc * ay;
-            rx = cc < h ? cc - h : ax + (cc - h);
+            __builtin_amdgcn_sched_barrier(0);
+            pull_finish<ST, MV>(a, C, co, rl, ridx(ox, oy), vo, s);
+            if (active) {
+                slot[fidx(tx, ty)] = aux_value(C, s, qs);
+                if (wlo) wq[0][fidx(tx, ty)] = qs;
+                if (whi) wq[1][fidx(tx, ty)] = qs;
+            }
         }
-        // periodic wrap without branches (the halo may wrap more than once
-        // around a box narrower than itself, but reaches at most 2 nodes out)
-        const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
-        NodeState hs;
-        fused_pull<ST, MV, WL>(a, C, rring, gx, gy, zp, rx, ry, zl, hs);
-        slot[fidx(rx, ry)] = aux_value(C, hs, qs);
-        if (wlo) wq[0][fidx(rx, ry)] = qs;
-        if (whi) wq[1][fidx(rx, ry)] = qs;
+    } else {
+        // 16-bit forms: the own node, then the halo node; fewer registers
+        // (3 waves per SIMD), measured faster for these forms
+        float qs;
+        if (active) {
+            const Coord co = make_coord_xyz<WL>(C, x0 + tx, y0 + ty, zp);
+            P vo[Q];
+            pull_issue<ST, CP_DEFAULT>(a, C, co, vo);
+            __builtin_amdgcn_sched_barrier(0);
+            pull_finish<ST, MV>(a, C, co, rl, ridx(tx, ty), vo, s);
+            slot[fidx(tx, ty)] = aux_value(C, s, qs);
+            if (wlo) wq[0][fidx(tx, ty)] = qs;
+            if (whi) wq[1][fidx(tx, ty)] = qs;
+        }
+        for (int eh = e; eh < nh; eh += 256) {
+            int rx, ry;
+            halo_pos(eh, w, nrow, h, ax, ay, rx, ry);
+            const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
+            const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
+            P vh[Q];
+            pull_issue<ST, CP_DEFAULT>(a, C, ch, vh);
+            __builtin_amdgcn_sched_barrier(0);
+            NodeState hs;
+            pull_finish<ST, MV>(a, C, ch, rl, ridx(rx, ry), vh, hs);
+            slot[fidx(rx, ry)] = aux_value(C, hs, qs);
+            if (wlo) wq[0][fidx(rx, ry)] = qs;
+            if (whi) wq[1][fidx(rx, ry)] = qs;
+        }
     }
 }
 
@@ -937,7 +988,12 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
                 const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
                 Stencil st = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 stencil_lds(ring, z, tx, ty, st);
-                collide_node<ST>(a, C, node, cur, st, ring[fslot(z)][fidx(tx, ty)].x);
+                // FP32 levels are stored non-temporally: the level is read
+                // back only by the next step, and the caches then keep the
+                // halo pulls of neighbouring tiles (measured +10 %); the 16-bit
+                // forms measured faster with ordinary stores
+                collide_node<ST, ST == LBCG_FP32 ? CP_STREAM : CP_DEFAULT>(a, C, node, cur, st,
+                                                                          ring[fslot(z)][fidx(tx, ty)].x);
             }
             cur = nxt;
         }

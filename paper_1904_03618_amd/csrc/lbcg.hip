@@ -490,8 +490,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     if (opt) o = *opt;
     if (o.graph_steps < 0) return fail(LBCG_EINVAL, "graph_steps must be >= 0");
     if (o.kernel < LBCG_KERNEL_AUTO || o.kernel > LBCG_KERNEL_FUSED) return fail(LBCG_EINVAL, "unknown kernel");
-    if (o.zchunk == 0) o.zchunk = 16;
-    if (o.zchunk < 1) return fail(LBCG_EINVAL, "zchunk must be >= 1");
+    if (o.zchunk < 0) return fail(LBCG_EINVAL, "zchunk must be >= 0");
     if (o.storage != LBCG_FP32 && o.storage != LBCG_FP16S && o.storage != LBCG_BF16S)
         return fail(LBCG_EINVAL, "unknown storage format");
     if (o.block_nodes == 0) o.block_nodes = 256;
@@ -546,11 +545,23 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
         delete h;
         return fail(LBCG_EINVAL, "fused kernel needs walls, if any, on the z axis");
     }
-    // The two-pass step is the faster one on gfx950 today (the fused kernel is
-    // latency-bound: its barrier-separated phases keep few loads in flight), so
-    // AUTO selects it.
-    h->fused = eligible && o.kernel == LBCG_KERNEL_FUSED;
+    // AUTO takes the fused step wherever it applies (measured faster than the
+    // two-pass step on the benchmark boxes) and the two-pass step otherwise.
+    h->fused = eligible && (o.kernel == LBCG_KERNEL_FUSED || o.kernel == LBCG_KERNEL_AUTO);
     h->zc = o.zchunk;
+    if (h->zc == 0) {
+        // default chunk: FP32 the longest of 16, 32, 64 planes that still
+        // leaves at least 512 tiles (two per CU); 16-bit forms 16 planes
+        // (measured best on the 128^3 and 128 x 128 x 512 boxes)
+        h->zc = 16;
+        if (o.storage == LBCG_FP32)
+            for (int zc : {32, 64}) {
+                int64_t n = 0;
+                for (const DevCase &d : h->dc)
+                    n += (int64_t)((d.nx + FTX - 1) / FTX) * ((d.ny + FTY - 1) / FTY) * ((d.nz + zc - 1) / zc);
+                if (n >= 512) h->zc = zc;
+            }
+    }
     h->graph_steps = o.graph_steps + (o.graph_steps & 1);
     std::vector<int4> ftiles;
     if (h->fused)

@@ -320,6 +320,19 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     return res
 
 
+def bench_summary(rt, gate=1.0):
+    """The fields of an experiment() summary that the benchmark reports."""
+    g = rt["gates"][str(gate)]
+    return {"lattice": rt["lattice"], "jump_steps": rt["every"], "heal_steps": rt["heal"], "steps": rt["steps"],
+            "train_amps": rt["train_amps"], "val_amp": rt["val_amp"], "eval_amp": rt["eval_amp"],
+            "train_iters": rt["train_iters"], "seeds": rt["seeds"], "selected_seed": rt["selected_seed"],
+            "selected_after": rt["selected_after"], "validation": rt["validation"], "train_s": rt["train_s"],
+            "loss_first": rt["loss_first"], "loss_last": rt["loss_last"], "gate_lu": gate,
+            "accepted": g["accepted"], "jumps": g["jumps"], "max_accepted_front_error": g["max_accepted_error"],
+            "final_front_error": g["final_front_error"], "lb_s": rt["lb_s"], "hybrid_s": g["hybrid_s"],
+            "gain": g["gain"], "persistence": g["persistence"]}
+
+
 def main(argv=None):
     import argparse
     import json

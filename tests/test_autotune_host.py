@@ -30,7 +30,8 @@ def test_fused_eligibility_and_candidates():
     p, fl = neutral_z[0]
     moving_z = [(dict(p, wall_u=((0.01, 0.0, 0.0), (0.0, 0.0, 0.0))), fl)]
     assert AT._fused_ok(periodic) and AT._fused_ok(neutral_z)
-    assert not AT._fused_ok(wetting_z) and not AT._fused_ok(wall_y) and not AT._fused_ok(moving_z)
+    assert AT._fused_ok(wetting_z) and AT._fused_ok(moving_z)
+    assert not AT._fused_ok(wall_y) and not AT._fused_ok(periodic + wall_y)
     with_f, without = AT.candidates(True), AT.candidates(False)
     assert any(c["kernel"] == "fused" for c in with_f)
     assert all(c["kernel"] == "twopass" for c in without)

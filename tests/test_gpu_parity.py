@@ -233,9 +233,11 @@ def test_batched_cases_match_single_runs_and_oracle():
     cases = [W.impact_case(0, lmin=9, lmax=16), W.impact_case(5, lmin=9, lmax=16),
              W.random_state_case(12, 10, 11, seed=31, bc=(0, 0, 1), theta=(70.0, 130.0)),
              W.random_state_case(9, 14, 6, seed=32, bc=(0, 1, 0), rho_in=(10.0, 1.0), alpha=(0.92, 0.2))]
+    # the y-wall box keeps the batch on the two-pass step; the boxes run alone
+    # take the same kernel
     batch = gpu_run(cases, 200, persistent_blocks=64)
     for c, (p, fl) in enumerate(cases):
-        alone = gpu_run([(p, fl)], 200)[0]
+        alone = gpu_run([(p, fl)], 200, kernel="twopass")[0]
         for k in ("rhoR", "rhoB", "ux", "uy", "uz"):
             assert np.array_equal(batch[c][k], alone[k]), (c, k)
     batch20 = gpu_run(cases, 20, persistent_blocks=64)
@@ -310,6 +312,20 @@ def test_fused_kernel_matches_oracle(name):
     p, fl = maker()
     g = gpu_run([(p, fl)], steps, kernel="fused", zchunk=zchunk)[0]
     assert_parity(f"fused_{name}", g, oracle_run(p, fl, steps), p)
+
+
+def test_fused_batch_equals_single_runs():
+    """Uneven boxes (periodic and z-walls with wetting, extents not multiples
+    of the tile) in one fused launch equal their single-box fused runs bit
+    for bit: each tile reads only its own case."""
+    cases = [W.impact_case(0, lmin=9, lmax=16), W.impact_case(5, lmin=9, lmax=16),
+             W.random_state_case(12, 10, 11, seed=31, bc=(0, 0, 1), theta=(70.0, 130.0)),
+             W.random_state_case(21, 17, 6, seed=33, rho_in=(10.0, 1.0), alpha=(0.92, 0.2))]
+    batch = gpu_run(cases, 200, kernel="fused", zchunk=5)
+    for c, (p, fl) in enumerate(cases):
+        alone = gpu_run([(p, fl)], 200, kernel="fused", zchunk=5)[0]
+        for k in ("rhoR", "rhoB", "ux", "uy", "uz"):
+            assert np.array_equal(batch[c][k], alone[k]), (c, k)
 
 
 def test_fused_batch_of_uneven_cases():

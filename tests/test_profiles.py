@@ -14,12 +14,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_traffic_profiles_match_the_kernel_source():
     h = bench.kernel_source_hash()
     for storage in ("fp32", "fp16s"):
-        path = os.path.join(ROOT, "profiles", f"k_collide_{storage}_galilean128_traffic.json")
+        path = os.path.join(ROOT, "profiles", f"k_fused_{storage}_rt128x128x512_traffic.json")
         with open(path) as fh:
             d = json.load(fh)
         assert d["kernel_source_sha256_16"] == h, f"{path} was taken on other kernels; profile again"
         assert abs(d["bytes_per_launch"] - d["bytes_per_node"] * d["nodes"]) < 1.0
-        assert 0.95 < d["bytes_per_node"] / d["algorithmic_bytes_per_node"] < 1.2
+        assert 0.95 < d["bytes_per_node"] / d["design_bytes_per_node"] < 1.6
         assert all(c.startswith("rocprofv3 --pmc ") for c in d["commands"])
 
 
