@@ -62,6 +62,25 @@ int64_t sg_conv3d_bwd_weight_ws(const sg_view *dy, int32_t ci, int32_t k);
 int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask,
                          float *dw, float *db, float *ws, int64_t ws_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the weight and
+ * bias gradients of sg_conv3d_bwd_weight, computed by the same kernels with
+ * the same partial-sum plan (so the results are equal bit for bit), but with
+ * the partial sums in a scratch array inside the library instead of a
+ * caller workspace.  The scratch holds SG_NOALLOC_SCRATCH_BYTES (96 MiB) per
+ * GPU, reserved when the library's surrogate code is first loaded on that GPU
+ * and held until the process ends; the call allocates nothing.  A problem
+ * whose sg_conv3d_bwd_weight_ws() exceeds that size returns SG_EINVAL, as do
+ * the argument errors of sg_conv3d_bwd_weight.  hip_stream must belong to the
+ * calling thread's current device (the scratch of that device is used).  All
+ * calls on one GPU share its scratch: calls that overlap in time on that GPU
+ * (on different streams, or from different threads) race and give wrong
+ * gradients; calls in order on one stream are safe.  Every scratch entry that
+ * is read is first written by the same call, so nothing needs clearing. */
+#define SG_NOALLOC_SCRATCH_BYTES ((int64_t)96 << 20)
+int sg_conv3d_bwd_weight_noalloc(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask,
+                                 float *dw, float *db, void *hip_stream);
+
 /* dyb = BF16(dx * [y > 0]) (mask only when y != NULL): the gradient through
  * a ReLU, cast to the MFMA operand type.  dx: FP32 view, y: BF16 view, dyb:
  * BF16 view, all with the same shape. */

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "lbcg_surrogate.h"
 
@@ -867,6 +868,31 @@ inline bool same_pos(const sg_view *a, const sg_view *b) { return a->n == b->n &
 
 int status() { return hipGetLastError() == hipSuccess ? SG_OK : SG_EDEVICE; }
 
+// Scratch of the no-allocation weight gradient: a file-scope device array,
+// one copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is only a stand-in for the
+// symbol): the device address of each GPU's copy is looked up once, with
+// that GPU current, and kept.
+static __device__ __align__(256) float scratch[SG_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_on_current_device(float **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SG_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SG_EDEVICE;
+        g_scratch_ptr[dev] = static_cast<float *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return SG_OK;
+}
+
 }  // namespace sg
 
 using namespace sg;
@@ -972,7 +998,7 @@ static bool bwd_weight_args(const sg_view *x, const sg_view *dy, int32_t k, cons
 }
 
 // The weight-gradient kernels with the per-group partial sums in ws (at least
-// b.ws_floats floats).
+// b.ws_floats floats); shared by the workspace and the no-allocation entries.
 static int bwd_weight_launch(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw,
                              float *db, float *ws, const BwdPlan &b, hipStream_t st)
 {
@@ -1005,6 +1031,18 @@ int sg_conv3d_bwd_weight(const sg_view *x, const sg_view *dy, int32_t k, int32_t
     if (!bwd_weight_args(x, dy, k, dw) || !ws) return SG_EINVAL;
     const BwdPlan b = bwd_plan(dy, x->c, k);
     if (ws_bytes < b.ws_floats * (int64_t)sizeof(float)) return SG_EINVAL;
+    return bwd_weight_launch(x, dy, k, periodic_mask, dw, db, ws, b, (hipStream_t)hip_stream);
+}
+
+int sg_conv3d_bwd_weight_noalloc(const sg_view *x, const sg_view *dy, int32_t k, int32_t periodic_mask, float *dw,
+                                 float *db, void *hip_stream)
+{
+    if (!bwd_weight_args(x, dy, k, dw)) return SG_EINVAL;
+    const BwdPlan b = bwd_plan(dy, x->c, k);
+    if (b.ws_floats * (int64_t)sizeof(float) > SG_NOALLOC_SCRATCH_BYTES) return SG_EINVAL;
+    float *ws = nullptr;
+    const int rc = scratch_on_current_device(&ws);
+    if (rc != SG_OK) return rc;
     return bwd_weight_launch(x, dy, k, periodic_mask, dw, db, ws, b, (hipStream_t)hip_stream);
 }
 

@@ -38,6 +38,7 @@ class sg_view(C.Structure):
 
 
 SG_EXPORTS = ("sg_conv3d_fwd", "sg_weight_prep", "sg_conv3d_bwd_weight_ws", "sg_conv3d_bwd_weight",
+              "sg_conv3d_bwd_weight_noalloc",
               "sg_relu_bwd_cast", "sg_pool2_fwd", "sg_pool2_bwd", "sg_up2_fwd", "sg_up2_bwd", "sg_up2_cat_fwd", "sg_mse",
               "sg_adam", "sg_pack", "sg_unpack", "sg_lift")
 
@@ -55,6 +56,7 @@ def lib():
             "sg_weight_prep": [vp, i32, i32, i32, vp, vp, i32, i32, vp],
             "sg_conv3d_bwd_weight_ws": [V, i32, i32],
             "sg_conv3d_bwd_weight": [V, V, i32, i32, vp, vp, vp, i64, vp],
+            "sg_conv3d_bwd_weight_noalloc": [V, V, i32, i32, vp, vp, vp],
             "sg_relu_bwd_cast": [V, V, V, vp],
             "sg_pool2_fwd": [V, V, vp], "sg_pool2_bwd": [V, V, i32, vp],
             "sg_up2_fwd": [V, V, vp], "sg_up2_bwd": [V, V, i32, vp], "sg_up2_cat_fwd": [V, V, V, vp],

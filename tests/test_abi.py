@@ -64,6 +64,13 @@ def test_surrogate_entry_points_reject_mismatched_views():
     assert L.sg_conv3d_fwd(v(1, 4, 4, 4, 8), p, None, 24, 3, 0, 0, v(1, 4, 4, 4, 24), None, 0, None) == EINVAL
     assert L.sg_conv3d_fwd(v(1, 4, 4, 4, 8), p, None, 16, 5, 0, 0, v(1, 4, 4, 4, 16), None, 0, None) == EINVAL
     assert L.sg_conv3d_fwd(v(1, 4, 4, 4, 8), p, None, 16, 3, 0, 0, None, None, 0, None) == EINVAL
+    # no-allocation weight gradient: views checked as for the workspace form,
+    # and a problem whose partial sums exceed the library's scratch is refused
+    # before anything is launched
+    assert L.sg_conv3d_bwd_weight_noalloc(v(1, 4, 4, 4, 8), v(1, 4, 4, 2, 16), 3, 0, p, p, None) == EINVAL
+    big = S.sg_view(p, 8, 64, 64, 64, 256, 0, 256, 0)
+    assert L.sg_conv3d_bwd_weight_ws(C.byref(big), 256, 3) > (96 << 20)
+    assert L.sg_conv3d_bwd_weight_noalloc(C.byref(big), C.byref(big), 3, 0, p, p, None) == EINVAL
 
 
 def test_struct_layout_matches_header():
