@@ -1,0 +1,43 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (the default kernel choice and chunking): the GPU run against
+the FP64 oracle at the nodes stored by tests/golden/make_full_size.py
+(interface and bulk samples), at the standard tolerances (rho^N 1e-5, u 1e-6,
+colour densities 1e-5 rho^in), and the FP64 box sums.  The inputs are checked
+to be the ones the stored values were computed from."""
+import os
+
+import numpy as np
+import pytest
+
+import full_size_cases as FS
+from gpu_helpers import gpu_run
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL_N, TOL_U, TOL_RHO = 1e-5, 1e-6, 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("name", list(FS.CASES))
+def test_full_size_matches_stored_oracle_samples(name):
+    g = np.load(os.path.join(HERE, "golden", name + ".npz"))
+    maker, steps = FS.CASES[name]
+    p, fl = maker()
+    assert str(g["input_digest"]) == FS.input_digest(p, fl), "inputs differ from the stored oracle run"
+    assert int(g["steps"]) == steps
+    print(name, "run", steps, "steps", flush=True)
+    out = gpu_run([(p, fl)], steps)[0]
+    idx = g["idx"]
+    e = {k: float(np.abs(out[k][idx] - g[k]).max()) for k in ("rhoR", "rhoB", "rhoN", "ux", "uy", "uz")}
+    print(name, {k: f"{v:.2e}" for k, v in e.items()}, "nodes", idx.size, flush=True)
+    assert e["rhoN"] <= TOL_N, e
+    assert max(e["ux"], e["uy"], e["uz"]) <= TOL_U, e
+    assert e["rhoR"] <= TOL_RHO * p["rho_in"][0] and e["rhoB"] <= TOL_RHO * p["rho_in"][1], e
+    d, do = np.asarray(out["diag"]), g["diag"]
+    assert abs(d[0] - do[0]) <= 1e-6 * abs(do[0]) and abs(d[1] - do[1]) <= 1e-6 * abs(do[1]), (d, do)

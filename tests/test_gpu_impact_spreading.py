@@ -7,11 +7,7 @@ footprint) is compared with the Asai correlation the paper uses.  The paper
 does not give the gas viscosity; the gas takes mu_B = mu_R/10.  Each case runs
 until the footprint has shrunk 3 % below its maximum (about 36000 steps,
 a minute).
-
-Run as a script for the whole sweep:
-    python tests/test_gpu_impact_spreading.py --re 75,150,300,600,1000 [--visc-ratio 10]
 """
-import argparse
 import json
 import time
 
@@ -72,17 +68,3 @@ def test_maximum_spreading_follows_asai(Re):
     assert r["steps"] < 45000                       # the maximum was reached and passed
     assert abs(r["Dmax"] / r["asai"] - 1.0) < 0.08
     assert r["mass_drift"] < 1e-4
-
-
-def main():
-    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--re", default="75,150,300,600,1000")
-    ap.add_argument("--visc-ratio", type=float, default=10.0)
-    a = ap.parse_args()
-    rows = [max_spreading(float(v), a.visc_ratio, log=lambda m: print(m, flush=True)) for v in a.re.split(",")]
-    for r in rows:
-        print(json.dumps(r), flush=True)
-
-
-if __name__ == "__main__":
-    main()

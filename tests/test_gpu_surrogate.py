@@ -173,8 +173,10 @@ def test_elementwise_layers():
 @pytest.mark.parametrize("pmask", [3, 0])
 def test_unet_loss_and_gradients_match_oracle(pmask):
     """One forward/backward of the whole network on an 8^3 box (batch 2):
-    loss and every layer's weight and bias gradients against the FP64
-    reference that rounds to BF16 where the kernels store BF16."""
+    loss and every layer's weight and bias gradients, element by element,
+    against the FP64 reference that rounds to BF16 where the kernels store
+    BF16 (the remaining difference is FP32 accumulation order, which can flip
+    a BF16 rounding of an intermediate operand by 2^-8 relative)."""
     import torch
     from oracle import conv_ref as R
     from oracle import unet_ref as U
@@ -205,14 +207,16 @@ def test_unet_loss_and_gradients_match_oracle(pmask):
     print("out", err, "loss", net.loss[0].item(), loss, flush=True)
     assert ok, err
     assert abs(net.loss[0].item() - loss) < 1e-3 * loss
+    # per layer, element by element: the largest weight (bias) gradient error
+    # relative to the largest weight (bias) gradient of that layer
     for l in net.layers:
         gW, gb = grads[l.name]
         a, b = l.gw.cpu().numpy().astype(np.float64), gW
-        rel = np.linalg.norm(a - b) / max(1e-30, np.linalg.norm(b))
-        cos = float(np.sum(a * b) / max(1e-30, np.linalg.norm(a) * np.linalg.norm(b)))
-        relb = np.linalg.norm(l.gb.cpu().numpy() - gb) / max(1e-30, np.linalg.norm(gb))
-        print(l.name, "dW rel %.2e cos %.6f  db rel %.2e" % (rel, cos, relb), flush=True)
-        assert rel < 2e-2 and cos > 0.9995 and relb < 2e-2, l.name
+        ew = float(np.abs(a - b).max()) / max(1e-30, float(np.abs(b).max()))
+        ab = l.gb.cpu().numpy().astype(np.float64)
+        eb = float(np.abs(ab - gb).max()) / max(1e-30, float(np.abs(gb).max()))
+        print(l.name, "dW max-abs rel %.2e  db max-abs rel %.2e" % (ew, eb), flush=True)
+        assert ew < 1e-2 and eb < 1e-2, l.name
 
 
 def test_unet_training_reduces_loss():
