@@ -13,12 +13,14 @@ Pipeline
      pressure, and the predicted velocity) and the LB step continues for
      `heal` steps, which rebuild the non-equilibrium parts and the interface
      profile;
-  4. gate: a jump is accepted only while the bubble and spike fronts of the
-     prediction are within `gate` lattice units of the LB run's fronts at the
-     same time; a rejected jump is replaced by `every` plain LB steps.
-     Here the LB fronts come from a reference run of the same case, so the
-     gate measures the surrogate's error; it is not timed as part of the
-     hybrid.
+  4. gate: inside the timed hybrid, an interval of plain LB steps checks the
+     network on the current flow: its one-jump prediction over that interval
+     must put both fronts within `gate` lattice units of the LB fronts and
+     must have a phase-field error at most `skill` times the change of the
+     phase field over the interval (the error of keeping the state as it is);
+     after a passed check a few jumps follow, then the next LB interval checks
+     again.  A plain LB run of the same case is used only afterwards, untimed,
+     to state the actual front error of every jump.
 """
 from __future__ import annotations
 
@@ -121,11 +123,13 @@ def train(net, trajs, box, lag, iters=400, lr=1e-3, lr_min=1e-5, seed=0, it0=0, 
 
 
 def score(h):
-    """Model-selection key of a hybrid run: a run that ends within 1 l.u. of
-    the LB fronts beats one that does not; then more accepted jumps; then a
-    smaller final error."""
-    ok = bool(np.isfinite(h["final_front_error"]) and h["final_front_error"] <= 1.0)
-    return (ok, h["accepted"], -float(h["final_front_error"]) if np.isfinite(h["final_front_error"]) else -1e9)
+    """Model-selection key of a hybrid run on the validation case: a run that
+    ends within 1 l.u. of the LB fronts and whose jumps all stayed within
+    1 l.u. beats one that does not; then more jumps; then a smaller final
+    error."""
+    fin = h["final_front_error"]
+    ok = bool(np.isfinite(fin) and fin <= 1.0 and h["max_jump_error"] <= 1.0)
+    return (ok, h["jumps"], -float(fin) if np.isfinite(fin) else -1e9)
 
 
 def full_domain_net(trained, box):
@@ -181,58 +185,88 @@ def lb_time(p, fl, t_start, t_end):
         s.close()
 
 
-def hybrid(net, p, fl, ref_fronts, every, t_start, t_end, heal=20, gate=1.0, use_net=True):
-    """LB to t_start, then jumps of `every` steps (network prediction, or the
-    unchanged state when use_net is False) each followed by `heal` LB steps,
-    gated against the LB fronts; returns the record and the wall time after
-    t_start (the reference run that judges the jumps is not timed)."""
+def front_distance(a, b):
+    """Largest distance between the bubble and the spike fronts of two states."""
+    return max(abs(a[0] - b[0]), abs(a[1] - b[1]))
+
+
+def hybrid(net, p, fl, every, t_start, t_end, heal=20, gate=1.0, trust=3, skill=0.5, use_net=True,
+           ref_fronts=None):
+    """LB to t_start, then the gated hybrid up to t_end, timed as a whole.
+
+    The gate uses only the run's own data.  An interval of `every` plain LB
+    steps from state S_a to S_b is also a check: the network predicts S_b from
+    S_a; the check passes when the predicted fronts lie within `gate` lattice
+    units of the LB fronts and the L2 error of the predicted phase field is at
+    most `skill` times |rho^N(S_b) - rho^N(S_a)| (persistence scores exactly 1,
+    so a slowly moving front alone does not pass).  After a passed check up to
+    `trust` jumps follow (each: predict `every` steps
+    ahead, lift the prediction to populations, `heal` LB steps); then another
+    LB interval checks again.  A failed check leaves the run on LB intervals,
+    each of which is a new check.  With use_net=False the same gate runs with
+    persistence (the state left unchanged) in place of the network.
+
+    ref_fronts ({t: fronts} of a plain LB run, optional) is read only outside
+    the timed sections, to record the actual front error of every jump for
+    evaluation.  Returns the records, the wall time after t_start (checks
+    included) and the final front error against ref_fronts (if given)."""
     import torch
     box = (p["nx"], p["ny"], p["nz"])
     s = B.Solver([(p, fl)])
     s.step(t_start)
     torch.cuda.synchronize()
-    t, wall, rec = t_start, 0.0, []
+    t, wall, rec, checks, trusted = t_start, 0.0, [], [], 0
     try:
-        while t + every + heal <= t_end:
-            torch.cuda.synchronize()
-            c0 = time.time()
-            f, rho = _fields(s, with_rho=True)
-            pred = predict(net, f, box) if use_net else f
-            torch.cuda.synchronize()
-            wall += time.time() - c0
-            fb, fs = fronts(pred[0], box)
-            rb, rs = ref_fronts[t + every]
-            err = max(abs(fb - rb), abs(fs - rs))
-            ok = bool(np.isfinite(err) and err <= gate)
-            c0 = time.time()
-            if ok:
+        while t + every <= t_end:
+            if trusted > 0 and t + every + heal <= t_end:
+                c0 = time.time()
+                f, rho = _fields(s, with_rho=True)
                 if use_net:
-                    lift_and_set(s, pred, p, rho)
+                    lift_and_set(s, predict(net, f, box), p, rho)
+                s.step(heal)
+                torch.cuda.synchronize()
+                wall += time.time() - c0
+                t += every + heal
+                trusted -= 1
+                r = dict(t=t, accepted=True)
+                if ref_fronts is not None:
+                    r["front_error"] = front_distance(fronts(_fields(s)[0], box), ref_fronts[t])
+                rec.append(r)
             else:
+                c0 = time.time()
+                fa = _fields(s).clone()
                 s.step(every)
-            s.step(heal)
-            torch.cuda.synchronize()
-            wall += time.time() - c0
-            t += every + heal
-            rec.append(dict(t=t, accepted=ok, front_error=err))
+                fbf = _fields(s)
+                pred = predict(net, fa, box) if use_net else fa
+                err = front_distance(fronts(pred[0], box), fronts(fbf[0], box))
+                moved = float(torch.linalg.vector_norm(fbf[0] - fa[0]))
+                rel = float(torch.linalg.vector_norm(pred[0] - fbf[0])) / max(moved, 1e-30)
+                torch.cuda.synchronize()
+                wall += time.time() - c0
+                t += every
+                ok = bool(np.isfinite(err) and err <= gate and rel <= skill)
+                trusted = trust if ok else 0
+                checks.append(dict(t=t, check_error=err, skill=rel, passed=ok))
         c0 = time.time()
         if t < t_end:
             s.step(t_end - t)
         f = _fields(s)
         torch.cuda.synchronize()
         wall += time.time() - c0
-        fb, fs = fronts(f[0], box)
-        rb, rs = ref_fronts[t_end]
-        final = max(abs(fb - rb), abs(fs - rs))
+        final = front_distance(fronts(f[0], box), ref_fronts[t_end]) if ref_fronts is not None else float("nan")
     finally:
         s.close()
-    return dict(records=rec, wall_s=wall, final_front_error=final,
-                accepted=sum(r["accepted"] for r in rec), jumps=len(rec))
+    errs = [r["front_error"] for r in rec if "front_error" in r]
+    return dict(records=rec, checks=checks, wall_s=wall, final_front_error=final,
+                accepted=len(rec), jumps=len(rec), checks_run=len(checks),
+                checks_passed=sum(c["passed"] for c in checks),
+                max_jump_error=max(errs) if errs else 0.0,
+                jumps_within_gate=sum(1 for e in errs if e <= gate))
 
 
 def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, val_amp=0.045,
                iters=3000, segments=6, heal=20, rec=20, batch=4, slab=None, t_start=None, lr=1e-3, lr_min=1e-5,
-               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), log=None):
+               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), trust=3, skill=0.5, log=None):
     """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
     steps apart from snapshots every `rec` steps) in `segments` pieces of one
     cosine schedule, once per seed (initial weights and pair sampling); after
@@ -282,13 +316,14 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
             hs += train(net, trajs, box, every // rec, iters=n_it, lr=lr, lr_min=lr_min, seed=sd, it0=seg * per_seg,
                         total=iters, log=log)
             full.load_state(net.state_dict())
-            hv = hybrid(full, pv, flv, ref_val, every, t_start, steps, heal=heal, gate=1.0)
+            hv = hybrid(full, pv, flv, every, t_start, steps, heal=heal, gate=1.0, trust=trust, skill=skill,
+                        ref_fronts=ref_val)
             key = score(hv)
-            val.append(dict(seed=sd, iters=seg * per_seg + n_it, accepted=hv["accepted"],
+            val.append(dict(seed=sd, iters=seg * per_seg + n_it, jumps=hv["jumps"], max_jump_error=hv["max_jump_error"],
                             final_front_error=hv["final_front_error"]))
             if log:
-                log(f"validation seed {sd} after {val[-1]['iters']} iterations: accepted "
-                    f"{hv['accepted']}/{hv['jumps']}, final front error {hv['final_front_error']:.3f}")
+                log(f"validation seed {sd} after {val[-1]['iters']} iterations: {hv['jumps']} jumps "
+                    f"(largest error {hv['max_jump_error']:.3f}), final front error {hv['final_front_error']:.3f}")
             if best is None or key > best[0]:
                 best = (key, net.state_dict(), len(val) - 1)
         if not hist or hs[-1][1] < hist[-1][1]:
@@ -301,36 +336,39 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     res = dict(lattice=[p["nx"], p["ny"], p["nz"]], every=every, steps=steps, t_start=t_start, heal=heal,
                train_amps=list(train_amps), val_amp=val_amp, eval_amp=eval_amp, params=net.nparams, train_iters=iters,
                batch=batch, train_shape=list(net.shape), snapshot_every=rec, train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]),
-               seeds=list(seeds), validation=val, selected_after=val[best[2]]["iters"],
+               seeds=list(seeds), trust=trust, skill=skill, validation=val, selected_after=val[best[2]]["iters"],
                selected_seed=val[best[2]]["seed"], lb_s=lb, trajectory_s=gen, gates={})
     for g in gates:
-        hyb = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g)
-        per = hybrid(full, p, fl, ref, every, t_start, steps, heal=heal, gate=g, use_net=False)
-        acc = [r["front_error"] for r in hyb["records"] if r["accepted"]]
+        hyb = hybrid(full, p, fl, every, t_start, steps, heal=heal, gate=g, trust=trust, skill=skill, ref_fronts=ref)
+        per = hybrid(full, p, fl, every, t_start, steps, heal=heal, gate=g, trust=trust, skill=skill, use_net=False,
+                     ref_fronts=ref)
         res["gates"][str(g)] = dict(
-            hybrid_s=hyb["wall_s"], gain=lb / hyb["wall_s"], accepted=hyb["accepted"], jumps=hyb["jumps"],
-            final_front_error=hyb["final_front_error"], max_accepted_error=max(acc) if acc else 0.0,
-            records=[(r["t"], int(r["accepted"]), round(r["front_error"], 3)) for r in hyb["records"]],
-            persistence=dict(accepted=per["accepted"], final_front_error=per["final_front_error"],
-                             gain=lb / per["wall_s"]))
+            hybrid_s=hyb["wall_s"], gain=lb / hyb["wall_s"], jumps=hyb["jumps"], checks=hyb["checks_run"],
+            checks_passed=hyb["checks_passed"], simulated_by_jumps=hyb["jumps"] * (every + heal),
+            steps_after_start=steps - t_start, final_front_error=hyb["final_front_error"],
+            max_jump_error=hyb["max_jump_error"], jumps_within_gate=hyb["jumps_within_gate"],
+            records=[(r["t"], round(r["front_error"], 3)) for r in hyb["records"]],
+            check_errors=[(c["t"], round(c["check_error"], 3), round(c["skill"], 3)) for c in hyb["checks"]],
+            persistence=dict(jumps=per["jumps"], checks_passed=per["checks_passed"],
+                             final_front_error=per["final_front_error"], gain=lb / per["wall_s"]))
         if log:
-            log(f"gate {g}: accepted {hyb['accepted']}/{hyb['jumps']}, final front error "
-                f"{hyb['final_front_error']:.3f}, gain {lb / hyb['wall_s']:.2f}; persistence accepted "
-                f"{per['accepted']}, final {per['final_front_error']:.3f}")
+            log(f"gate {g}: {hyb['jumps']} jumps after {hyb['checks_passed']}/{hyb['checks_run']} passed checks, "
+                f"{hyb['jumps_within_gate']} within the gate, largest jump error {hyb['max_jump_error']:.3f}, "
+                f"final front error {hyb['final_front_error']:.3f}, gain {lb / hyb['wall_s']:.2f}; persistence "
+                f"{per['jumps']} jumps, final {per['final_front_error']:.3f}")
     return res
 
 
 def bench_summary(rt, gate=1.0):
     """The fields of an experiment() summary that the benchmark reports."""
     g = rt["gates"][str(gate)]
-    return {"lattice": rt["lattice"], "jump_steps": rt["every"], "heal_steps": rt["heal"], "steps": rt["steps"],
-            "train_amps": rt["train_amps"], "val_amp": rt["val_amp"], "eval_amp": rt["eval_amp"],
-            "train_iters": rt["train_iters"], "seeds": rt["seeds"], "selected_seed": rt["selected_seed"],
-            "selected_after": rt["selected_after"], "validation": rt["validation"], "train_s": rt["train_s"],
-            "loss_first": rt["loss_first"], "loss_last": rt["loss_last"], "gate_lu": gate,
-            "accepted": g["accepted"], "jumps": g["jumps"], "max_accepted_front_error": g["max_accepted_error"],
-            "final_front_error": g["final_front_error"], "lb_s": rt["lb_s"], "hybrid_s": g["hybrid_s"],
-            "gain": g["gain"], "persistence": g["persistence"]}
+    keep = ("lattice", "every", "heal", "steps", "t_start", "trust", "skill", "train_amps", "val_amp", "eval_amp",
+            "train_iters", "seeds", "selected_seed", "selected_after", "train_s", "loss_first", "loss_last", "lb_s")
+    out = {k: rt[k] for k in keep}
+    out.update(gate_lu=gate, **{k: g[k] for k in ("hybrid_s", "gain", "jumps", "checks", "checks_passed",
+                                                   "simulated_by_jumps", "steps_after_start", "final_front_error",
+                                                   "max_jump_error", "jumps_within_gate", "persistence")})
+    return out
 
 
 def main(argv=None):
@@ -347,11 +385,14 @@ def main(argv=None):
     ap.add_argument("--slab", type=int, default=0, help="train on z-slabs of this depth (0: whole box)")
     ap.add_argument("--segments", type=int, default=6)
     ap.add_argument("--seeds", default="7,8,9,10,11,12", help="training seeds; the validation picks across all of them")
+    ap.add_argument("--trust", type=int, default=3, help="jumps after each passed check")
+    ap.add_argument("--skill", type=float, default=0.5, help="largest phase-field error of a passed check, "
+                                                            "relative to the change over the interval")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
     res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, rec=a.rec, slab=a.slab or None,
-                     segments=a.segments, seeds=tuple(int(v) for v in a.seeds.split(",")),
-                     log=lambda m: print(m, flush=True))
+                     segments=a.segments, seeds=tuple(int(v) for v in a.seeds.split(",")), trust=a.trust,
+                     skill=a.skill, log=lambda m: print(m, flush=True))
     txt = json.dumps(res)
     print(txt, flush=True)
     if a.out:
