@@ -4,7 +4,7 @@
 Headline workload: the 3D Rayleigh-Taylor instability (Sec. IV.C) on a
 128 x 128 x 512 D3Q19 lattice, walls on z, periodic sides, Atwood number 0.5
 (rho^in 3/1), gravity 2e-5, Re = 1024, single-mode perturbation of amplitude
-0.05 L, plain FP32 populations; the largest single-GPU configuration of the
+0.05 L, FP32 arithmetic and storage; the largest single-GPU configuration of the
 benchmark set.  A step is one full time step of the method (moments, colour
 gradient, MRT collision with correction term and perturbation, recoloring,
 streaming with bounce-back walls).  Beside it: the same case scaled to
@@ -33,9 +33,12 @@ POP = {"fp32": 4, "fp16s": 2, "bf16s": 2}
 # Algorithmic HBM bytes per fluid node and step of the method: 38
 # populations read and 38 written (the figure the roofline is priced at).
 ALGO_BYTES = {k: 2 * 38 * b for k, b in POP.items()}
-# What the fused step moves by design: the populations plus the colour
-# densities each writer stores with its values (8 B read, 8 B written).
-FUSED_BYTES = {k: 2 * (38 * b + 8) for k, b in POP.items()}
+# What the fused step moves by design, per level format: pairs move the 38
+# populations plus the colour densities each writer stores with them (8 B
+# read, 8 B written); the compact format moves 20 population values (the
+# rest pair and 18 totals) plus 7 FP32 words of writer data, read and written.
+FUSED_BYTES = {"pair": {k: 2 * (38 * b + 8) for k, b in POP.items()},
+               "compact": {k: 2 * (20 * b + 28) for k, b in POP.items()}}
 # The two-pass step: populations and stored densities read twice (moments
 # pass, collision pass), the aux value written once and read once.
 TWOPASS_BYTES = {k: 3 * (38 * b + 8) + 2 * 16 for k, b in POP.items()}
@@ -64,14 +67,18 @@ def measured_traffic(kernel, storage, workload):
             "file": os.path.relpath(path, ROOT)}
 
 
-def timed_run(B, cases, storage, steps, warmup, kernel_steps=100, repeats=0, repeat_steps=200, **opts):
+def timed_run(B, cases, storage, steps, warmup, kernel_steps=100, repeats=0, repeat_steps=200, layout=None,
+              **opts):
     """Time `steps` steps with HIP events on the handle's stream (no
     per-kernel events inside), then `repeats` further runs, then
     `kernel_steps` steps with event pairs around every kernel.  Returns
     (ms per step, per-kernel average ms, repeat ms list, fields of case 0
-    after the timed steps, the options the handle reports)."""
+    after the timed steps); `layout` (a dict) receives the step kernel and
+    level format the handle resolved."""
     import torch
     s = B.Solver(cases, storage=storage, **opts)
+    if layout is not None:
+        layout.update(kernel=B.lbcg_step_kernel(s.h), level=B.lbcg_level_format(s.h))
     try:
         stream = torch.cuda.current_stream()
         s.step(warmup)
@@ -103,16 +110,17 @@ def timed_run(B, cases, storage, steps, warmup, kernel_steps=100, repeats=0, rep
         s.close()
 
 
-def roofline(kernels, storage, N, ms_step, twopass):
+def roofline(kernels, storage, N, ms_step, level="pair"):
     """Roofline of the dominant kernel (the fused step, or the two-pass
     collision pass) at the method's algorithmic bytes, and the step's."""
     if "k_fused" in kernels:
-        name, kms, design = "k_fused", kernels["k_fused"], FUSED_BYTES[storage]
+        name, kms, design = "k_fused", kernels["k_fused"], FUSED_BYTES[level][storage]
     else:
         name, kms, design = "k_collide", kernels.get("k_collide", ms_step), TWOPASS_BYTES[storage]
     ach = ALGO_BYTES[storage] * N / (kms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBPS,
-            "kernel": f"{name}<{storage}>", "kernel_avg_ms": kms, "bytes_per_node": ALGO_BYTES[storage],
+            "kernel": f"{name}<{storage}>", "level_format": level if name == "k_fused" else "pair",
+            "kernel_avg_ms": kms, "bytes_per_node": ALGO_BYTES[storage],
             "design_bytes_per_node": design if name == "k_fused" else None,
             "design_GBps": design * N / (kms * 1e-3) / 1e9 if name == "k_fused" else None,
             "step_achieved": ALGO_BYTES[storage] * N / (ms_step * 1e-3) / 1e9,
@@ -272,17 +280,20 @@ def main():
     N = p["nx"] * p["ny"] * p["nz"]
     cases = [(p, fl)]
 
-    ms, kt, reps, ref = timed_run(B, cases, "fp32", args.steps, args.warmup, repeats=args.repeats, kernel=args.kernel)
+    lay = {}
+    ms, kt, reps, ref = timed_run(B, cases, "fp32", args.steps, args.warmup, repeats=args.repeats, layout=lay,
+                                  kernel=args.kernel)
     mlups = N / (ms * 1e-3) / 1e6
-    roof = roofline(kt, "fp32", N, ms, args.kernel == "twopass")
+    roof = roofline(kt, "fp32", N, ms, lay["level"])
     roof["traffic"] = measured_traffic(roof["kernel"].split("<")[0], "fp32", "rt128x128x512")
 
     forms = {}
     for st in [s for s in args.forms.split(",") if s]:
-        fms, fkt, _, ff = timed_run(B, cases, st, args.steps, args.warmup, kernel=args.kernel)
+        flay = {}
+        fms, fkt, _, ff = timed_run(B, cases, st, args.steps, args.warmup, layout=flay, kernel=args.kernel)
         err_n = float((ff["rhoN"] - ref["rhoN"]).abs().max())
         err_u = float(max((ff[k] - ref[k]).abs().max() for k in ("ux", "uy", "uz")))
-        froof = roofline(fkt, st, N, fms, args.kernel == "twopass")
+        froof = roofline(fkt, st, N, fms, flay["level"])
         froof["traffic"] = measured_traffic(froof["kernel"].split("<")[0], st, "rt128x128x512")
         forms[st] = {"MLUPS": N / (fms * 1e-3) / 1e6, "ms_per_step": fms, "kernels_avg_ms": fkt,
                      "roofline": froof, "vs_fp32": N / (fms * 1e-3) / 1e6 / mlups,
@@ -295,10 +306,11 @@ def main():
         NL = pl["nx"] * pl["ny"] * pl["nz"]
         big = {}
         for st in ("fp32", "fp16s"):
-            lms, lkt, _, _ = timed_run(B, [(pl, fll)], st, min(args.steps, 100), 5, kernel_steps=20,
+            llay = {}
+            lms, lkt, _, _ = timed_run(B, [(pl, fll)], st, min(args.steps, 100), 5, kernel_steps=20, layout=llay,
                                        kernel=args.kernel)
             big[st] = {"MLUPS": NL / (lms * 1e-3) / 1e6, "ms_per_step": lms, "kernels_avg_ms": lkt,
-                       "roofline": roofline(lkt, st, NL, lms, args.kernel == "twopass")}
+                       "roofline": roofline(lkt, st, NL, lms, llay["level"])}
         del fll
         extra["rayleigh_taylor_256x256x1024"] = big
     if args.galilean:
@@ -306,9 +318,10 @@ def main():
         NG = 128 ** 3
         gal = {}
         for st in ("fp32", "fp16s"):
-            gms, gkt, _, _ = timed_run(B, [(pg, flg)], st, args.steps, args.warmup, kernel=args.kernel)
+            glay = {}
+            gms, gkt, _, _ = timed_run(B, [(pg, flg)], st, args.steps, args.warmup, layout=glay, kernel=args.kernel)
             gal[st] = {"MLUPS": NG / (gms * 1e-3) / 1e6, "ms_per_step": gms, "kernels_avg_ms": gkt,
-                       "roofline": roofline(gkt, st, NG, gms, args.kernel == "twopass")}
+                       "roofline": roofline(gkt, st, NG, gms, glay["level"])}
         extra["galilean_droplet_128"] = gal
 
     copy = copy_probe(args.copy_probe_mib) if args.copy_probe_mib > 0 else None
@@ -320,7 +333,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "rayleigh-taylor 128x128x512 (walls on z, At 0.5, g 2e-5, Re 1024, amplitude 0.05 L)",
-                   "lattice": [128, 128, 512], "storage": "fp32", "kernel": args.kernel,
+                   "lattice": [128, 128, 512], "storage": "fp32", "kernel": lay["kernel"],
+                   "level_format": lay["level"],
                    "tau_v": list(p["tau_v"]), "parallelism": "single GPU"},
         "repeat_runs": {"runs": len(reps), "steps": 200, "ms_per_step": reps,
                         "median_MLUPS": N / (float(np.median(reps)) * 1e-3) / 1e6 if reps else None},

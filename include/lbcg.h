@@ -115,6 +115,18 @@ typedef struct lbcg_fields {
                                    walls, or walls on the z axis (any contact
                                    angle, at rest or moving) */
 
+/* Level formats (how a time level is stored between steps). */
+#define LBCG_LEVEL_AUTO 0       /* FP32 with the fused step: compact; otherwise pairs */
+#define LBCG_LEVEL_PAIR 1       /* every direction stores its red and blue deviation */
+#define LBCG_LEVEL_COMPACT 2    /* fused step only: direction 0 stores both colours,
+                                   directions 1-18 only the total deviation, and each
+                                   node 7 FP32 words from which the reader rebuilds the
+                                   red share exactly as the recoloring (Eq. 10-11)
+                                   split it; 27 words per node and level in FP32
+                                   instead of 40.  The start level and a level written
+                                   by lbcg_set_fields are pairs; the first step
+                                   after them writes the compact format. */
+
 /* Handle-wide options.  storage: LBCG_FP32 / LBCG_FP16S / LBCG_BF16S.
  * diag_every: run the stability check every this many steps inside
  * lbcg_step (0 = never).  block_nodes: nodes per work tile and workgroup of
@@ -127,7 +139,9 @@ typedef struct lbcg_fields {
  * graph_steps: 0 = launch every kernel of every step; n > 0 = capture n steps
  * (rounded up to even) once into a HIP graph and replay it; with diag_every
  * the stability check then runs at the first replay boundary at or after each
- * multiple of diag_every, and kernel timing (lbcg_timing) is not available. */
+ * multiple of diag_every, and kernel timing (lbcg_timing) is not available.
+ * level: LBCG_LEVEL_*; LBCG_LEVEL_COMPACT with the two-pass step (asked for,
+ * or the only one the cases allow) is LBCG_EINVAL. */
 typedef struct lbcg_options {
     int32_t storage;
     int32_t diag_every;
@@ -136,7 +150,7 @@ typedef struct lbcg_options {
     int32_t kernel;
     int32_t zchunk;
     int32_t graph_steps;
-    int32_t reserved;
+    int32_t level;
 } lbcg_options;
 
 typedef struct lbcg_handle lbcg_handle;
@@ -223,9 +237,14 @@ int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f);
 int lbcg_timing(lbcg_handle *h, int32_t enable);
 int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches);
 
-/* Number of nodes and storage bytes per population value of the handle. */
+/* Number of nodes and storage bytes per population value of the handle;
+ * the handle's step kernel (LBCG_KERNEL_TWOPASS or LBCG_KERNEL_FUSED) and
+ * level format (LBCG_LEVEL_PAIR or LBCG_LEVEL_COMPACT) as resolved at init.
+ * -1 for an invalid handle or case. */
 int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id);
 int32_t lbcg_storage_bytes(const lbcg_handle *h);
+int32_t lbcg_step_kernel(const lbcg_handle *h);
+int32_t lbcg_level_format(const lbcg_handle *h);
 
 /* Checkpoint / resume.  The state of a handle at its current level is the
  * stored population values of every case (raw bits, storage format of the

@@ -34,6 +34,20 @@ __host__ __device__ constexpr int ecls(int i) { return i == 0 ? 0 : (i <= 6 ? 1 
 // the direction with e_opp = -e_i (pairs (1,2), (3,4), ... (17,18))
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 == 1 ? i + 1 : i - 1); }
 
+// Level formats.  PAIR: every direction stores its red and blue deviation
+// (Storage::P per node and direction).  COMPACT: direction 0 stores the pair,
+// directions 1-18 store only the total deviation t_i = sum_k d_i^k
+// (Storage::T), and each writer stores, besides its densities, the data from
+// which a puller rebuilds the red share of any of its values exactly as the
+// recoloring (Eq. 10-11) defines it: d_i^R = (rho_R/rho) t_i + seg_i + cr_c,
+// with seg_i = e_i . g on the axes and kDiagSeg e_i . g on the diagonals
+// (g = beta rho_R rho_B p n / (6 rho^2)), cr the class share of the rest
+// state and of the densities' FP32 remainders (cr on the diagonals is half
+// the axis value, as phi^k is).  A COMPACT level moves 20 + 7 words per node
+// and level instead of 38 + 2 (20 population values plus 7 FP32 words).
+constexpr int LV_PAIR = 0, LV_COMPACT = 1;
+constexpr float kDiagSeg = 0.35355339059327378f;        // (1/2) cos 45 deg
+
 // Population storage.  Every format keeps deviations d = f - rho_k phi_i^k
 // from the rest state of the node that wrote the value (rho_k: that node's
 // colour density, kept per node in FP32), scaled by 2^s for FP16.  The node's
@@ -109,10 +123,13 @@ __device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, T val
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, val), r, (int)byte_off, 0, CP);
     } else if constexpr (sizeof(T) == 4) {
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, val), r, (int)byte_off, 0, CP);
-    } else {
-        static_assert(sizeof(T) == 8, "buffer element size");
+    } else if constexpr (sizeof(T) == 8) {
         typedef unsigned u2 __attribute__((ext_vector_type(2)));
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, val), r, (int)byte_off, 0, CP);
+    } else {
+        static_assert(sizeof(T) == 16, "buffer element size");
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, val), r, (int)byte_off, 0, CP);
     }
 }
 
@@ -149,6 +166,10 @@ struct StepArgs {
     float4 *ghost;               // per wall-plane node: same fields one layer beyond the wall
     const float2 *rho_prev;      // rho_R, rho_B the writers of fin stored with their values
     float2 *rho_cur;             // rho_R, rho_B stored with fout
+    const float4 *dsc_prev;      // compact levels: the writers' recoloring data of fin
+    float4 *dsc_cur;             //   (rho_R/rho, g_x, g_y, g_z) stored with fout
+    const float *crs_prev;       //   and the axis-class rest-share term
+    float *crs_cur;
     float *wallq;                // per ghost entry: sum_k rho_k (1 - 3 c_s^k^2) of the first layer
     const DevCase *cases;
     const int2 *tiles;           // (case, first node) per tile

@@ -318,6 +318,178 @@ __device__ inline void pull_finish(const StepArgs &a, DC &C, const Coord &c, con
     s.eta[1] = eB - s.D[1];
 }
 
+// ------------------------------------------------------ compact levels
+// A compact level (LV_COMPACT in d3q19.hpp): direction 0 is the writer's own
+// (red, blue) pair at pair index node; direction i >= 1 is one total
+// deviation at element (i + 1) NS + node, so i and its opposite are again
+// adjacent arrays.  A puller rebuilds the red share of each value from the
+// writer's data (rho_R, rho_B; rho_R/rho, g; cr) exactly as the writer's
+// recoloring defines it, and the blue share as the rest of the total.
+
+// e_i . (d.y, d.z, d.w)
+template <int I>
+__device__ inline float e_dot(const float4 &d)
+{
+    constexpr int X = ex(I), Y = ey(I), Z = ez(I);
+    if constexpr (X != 0 && Y != 0) return X * d.y + Y * d.z;
+    else if constexpr (X != 0 && Z != 0) return X * d.y + Z * d.w;
+    else if constexpr (Y != 0 && Z != 0) return Y * d.z + Z * d.w;
+    else if constexpr (X != 0) return X * d.y;
+    else if constexpr (Y != 0) return Y * d.z;
+    else return Z * d.w;
+}
+
+// One pulled value t of direction I >= 1 with its writer's data (rw: rho_R,
+// rho_B; dw: rho_R/rho, g; cw: axis-class cr).  bb: the value is the node's
+// own opposite direction (halfway bounce-back), whose segregation term has
+// the opposite sign.
+template <int ST, bool MV, int I>
+__device__ inline void decode_c(DC &C, const Coord &c, const float2 own, bool bb, float t, float2 rw, float4 dw,
+                                float cw, NodeState &s, float &eR, float &eB)
+{
+    constexpr int cl = ecls(I);
+    const float eg = e_dot<I>(dw);
+    float seg = cl == 1 ? eg : kDiagSeg * eg;
+    if (bb) seg = -seg;
+    const float crc = cl == 1 ? cw : 0.5f * cw;
+    const float dR = __builtin_fmaf(dw.x, t, seg + crc);
+    float tR = __builtin_fmaf(rw.x - own.x, C.phi[0][cl], dR);
+    float tB = __builtin_fmaf(rw.y - own.y, C.phi[1][cl], t - dR);
+    if constexpr (MV) {
+        if (C.moving && bb) {        // moving wall: the reflected population gains its momentum
+            const float eu = wall_eu<I>(C, bounce_side<I>(c));
+            tR = __builtin_fmaf(eu * C.wg[0][cl - 1], own.x, tR);
+            tB = __builtin_fmaf(eu * C.wg[1][cl - 1], own.y, tB);
+        }
+    }
+    const float h = tR + tB;
+    s.h[I] = h;
+    eR += tR;
+    eB += tB;
+    if constexpr (ex(I) == 1) s.jx += h;
+    if constexpr (ex(I) == -1) s.jx -= h;
+    if constexpr (ey(I) == 1) s.jy += h;
+    if constexpr (ey(I) == -1) s.jy -= h;
+    if constexpr (ez(I) == 1) s.jz += h;
+    if constexpr (ez(I) == -1) s.jz -= h;
+}
+
+// Loaded values of one compact pull: the own pair of direction 0 and the
+// totals of directions 1-18 (v[0] unused).
+template <int ST> struct CompactPull {
+    typename Storage<ST>::P v0;
+    typename Storage<ST>::T v[Q];
+};
+
+template <int ST, int CPP, int I = 1>
+__device__ inline void pull_issue_c(const StepArgs &a, DC &C, const Coord &c, CompactPull<ST> &p)
+{
+    using S = Storage<ST>;
+    using T = typename S::T;
+    using P = typename S::P;
+    const size_t NS = (size_t)C.NS;
+    const T *base0 = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+    if constexpr (I == 1)
+        p.v0 = buf_ld<P, CPP>(rsrc(base0, NS * sizeof(P)), (uint32_t)c.node * (uint32_t)sizeof(P));
+    if constexpr (I < Q) {
+        constexpr int F = pair_first<I>();
+        const bool bb = bounce<I>(c);
+        const uint32_t si = (uint32_t)(bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c));
+        constexpr bool hi_own = I != F, hi_opp = opp(I) != F;
+        const bool hi = bb ? hi_opp : hi_own;
+        const uint32_t e = si + (hi ? (uint32_t)NS : 0u);
+        p.v[I] = buf_ld<T, CPP>(rsrc(base0 + (size_t)(F + 1) * NS, 2 * NS * sizeof(T)), e * (uint32_t)sizeof(T));
+        pull_issue_c<ST, CPP, I + 1>(a, C, c, p);
+    }
+}
+
+// LDS rings of the writers' data of planes z-1, z, z+1 (as the density ring).
+struct WriterRing {
+    const float2 *r[3];
+    const float4 *d[3];
+    const float *c[3];
+};
+
+template <int ST, bool MV, int I = 1>
+__device__ inline void pull_decode_c(const StepArgs &a, DC &C, const Coord &c, const float2 own,
+                                     const WriterRing &wr, int ri, const CompactPull<ST> &p, NodeState &s,
+                                     float &eR, float &eB)
+{
+    if constexpr (I < Q) {
+        using S = Storage<ST>;
+        const bool bb = bounce<I>(c);
+        const int li = bb ? ri : ri - ex(I) - RW * ey(I);
+        const float2 *R = bb ? wr.r[1] : wr.r[1 - ez(I)];
+        const float4 *D = bb ? wr.d[1] : wr.d[1 - ez(I)];
+        const float *Cw = bb ? wr.c[1] : wr.c[1 - ez(I)];
+        decode_c<ST, MV, I>(C, c, own, bb, S::dec(p.v[I], a.inv_scale), R[li], D[li], Cw[li], s, eR, eB);
+        pull_decode_c<ST, MV, I + 1>(a, C, c, own, wr, ri, p, s, eR, eB);
+    }
+}
+
+template <int ST>
+__device__ inline void own_pair(const StepArgs &a, const typename Storage<ST>::P &v0, NodeState &s, float &eR,
+                                float &eB)
+{
+    using S = Storage<ST>;
+    const float dR = S::dec(v0.r, a.inv_scale), dB = S::dec(v0.b, a.inv_scale);
+    s.h[0] = dR + dB;
+    eR = dR;
+    eB = dB;
+}
+
+__device__ inline void finish_state(const float2 own, float eR, float eB, NodeState &s)
+{
+    s.R[0] = own.x + eR;
+    s.R[1] = own.y + eB;
+    s.D[0] = s.R[0] - own.x;
+    s.D[1] = s.R[1] - own.y;
+    s.eta[0] = eR - s.D[0];
+    s.eta[1] = eB - s.D[1];
+}
+
+// The node state from a compact pull, writers' data from the LDS rings.
+template <int ST, bool MV>
+__device__ inline void pull_finish_c(const StepArgs &a, DC &C, const Coord &c, const WriterRing &wr, int ri,
+                                     const CompactPull<ST> &p, NodeState &s)
+{
+    const float2 own = wr.r[1][ri];
+    float eR, eB;
+    s.jx = s.jy = s.jz = 0.f;
+    own_pair<ST>(a, p.v0, s, eR, eB);
+    pull_decode_c<ST, MV>(a, C, c, own, wr, ri, p, s, eR, eB);
+    finish_state(own, eR, eB, s);
+}
+
+// The same with the writers' data read from memory (diagnostics).
+template <int ST, bool MV, int I = 1>
+__device__ inline void pull_mem_c(const StepArgs &a, DC &C, const Coord &c, const float2 own,
+                                  const CompactPull<ST> &p, NodeState &s, float &eR, float &eB)
+{
+    if constexpr (I < Q) {
+        using S = Storage<ST>;
+        const bool bb = bounce<I>(c);
+        const int si = bb ? c.node : neighbour<-ex(I), -ey(I), -ez(I)>(c);
+        const size_t o = (size_t)C.node_off + si;
+        decode_c<ST, MV, I>(C, c, own, bb, S::dec(p.v[I], a.inv_scale), a.rho_prev[o], a.dsc_prev[o],
+                            a.crs_prev[o], s, eR, eB);
+        pull_mem_c<ST, MV, I + 1>(a, C, c, own, p, s, eR, eB);
+    }
+}
+
+template <int ST, bool MV>
+__device__ inline void pull_node_c(const StepArgs &a, DC &C, const Coord &c, NodeState &s)
+{
+    CompactPull<ST> p;
+    pull_issue_c<ST, CP_DEFAULT>(a, C, c, p);
+    const float2 own = a.rho_prev[C.node_off + c.node];
+    float eR, eB;
+    s.jx = s.jy = s.jz = 0.f;
+    own_pair<ST>(a, p.v0, s, eR, eB);
+    pull_mem_c<ST, MV>(a, C, c, own, p, s, eR, eB);
+    finish_state(own, eR, eB, s);
+}
+
 // CPP: cache policy of the population loads (streaming unless the same
 // populations are read again soon).
 template <int ST, bool MV, int CPP = CP_STREAM>
@@ -488,7 +660,10 @@ __device__ inline float tau_v(DC &C, float rn)
 // correction term, body force and perturbation (Eq. 41-45, 53), recoloring
 // (Eq. 10-11) and the store of both colours' deviations at the node's own
 // slots.  st: colour gradient and Q_alpha (Eq. 49); rn: the node's rho^N.
-template <int ST, int CPS = CP_DEFAULT>
+// OUT: level format written (LV_PAIR, or LV_COMPACT: the total deviations
+// plus the writer's recoloring data, from which the pullers rebuild the red
+// shares this function would have stored).
+template <int ST, int CPS = CP_DEFAULT, int OUT = LV_PAIR>
 __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const NodeState &s,
                                     const Stencil &st, float rn)
 {
@@ -646,8 +821,31 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     const float ar = RR / rho;
     const float bseg = C.beta * RR * RB * ir * ir;
     const float sa = bseg * p * (1.0f / 6.0f);
-    const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
     const float rr = RR * RB;
+    using P = typename S::P;
+    const size_t N = (size_t)C.N, NS = (size_t)C.NS;
+    if constexpr (OUT == LV_COMPACT) {
+        // direction 0 as a pair, directions 1-18 as totals, the writer's data
+        const float cr0 = (rr * (C.phi[1][0] - C.phi[0][0]) + s.eta[0] * RB * C.phi[1][0] -
+                           s.eta[1] * RR * C.phi[0][0]) * ir;
+        const float cr1 = (rr * (C.phi[1][1] - C.phi[0][1]) + s.eta[0] * RB * C.phi[1][1] -
+                           s.eta[1] * RR * C.phi[0][1]) * ir;
+        const uint32_t off = (uint32_t)node * (uint32_t)sizeof(T);
+        T *tb = reinterpret_cast<T *>(a.fout) + C.pop_off;
+        const float dr0 = ar * fs[0] + cr0;
+        buf_st<P, CPS>(rsrc(tb, NS * sizeof(P)), (uint32_t)node * (uint32_t)sizeof(P),
+                       P{S::enc(dr0, a.scale), S::enc(fs[0] - dr0, a.scale)});
+        #pragma unroll
+        for (int i = 1; i < Q; ++i)
+            buf_st<T, CPS>(rsrc(tb + (size_t)(i + 1) * NS, NS * sizeof(T)), off, S::enc(fs[i], a.scale));
+        buf_st<float2, CPS>(rsrc(a.rho_cur + C.node_off, N * sizeof(float2)), (uint32_t)node * 8u,
+                            make_float2(RR, RB));
+        buf_st<float4, CPS>(rsrc(a.dsc_cur + C.node_off, N * sizeof(float4)), (uint32_t)node * 16u,
+                            make_float4(ar, sa * nx, sa * ny, sa * nz));
+        buf_st<float, CPS>(rsrc(a.crs_cur + C.node_off, N * sizeof(float)), (uint32_t)node * 4u, cr1);
+        return;
+    }
+    const float sd = bseg * p * (1.0f / 12.0f) * 0.70710678118654752f;
     float cr[3];
     #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -660,9 +858,7 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     seg[11] = sd * (nx + nz); seg[12] = -seg[11]; seg[13] = sd * (nx - nz); seg[14] = -seg[13];
     seg[15] = sd * (ny + nz); seg[16] = -seg[15]; seg[17] = sd * (ny - nz); seg[18] = -seg[17];
 
-    using P = typename S::P;
     P *outb = reinterpret_cast<P *>(a.fout) + C.pop_off / 2;
-    const size_t N = (size_t)C.N, NS = (size_t)C.NS;
     #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const float dr = ar * fs[i] + seg[i] + cr[ecls(i)];
@@ -742,12 +938,20 @@ __device__ inline int ridx(int rx, int ry) { return (rx + RH) + RW * (ry + RH); 
 // Split into the loads (two rounds of at most RREG = 484 entries, issued
 // together and early) and the LDS stores, so that their latency hides behind
 // the pulls issued in between.
-struct RhoStage { float2 v[2]; int d[2]; };
+// IN = LV_COMPACT: the writers' recoloring data are staged the same way into
+// rings of their own.
+template <int IN> struct RhoStage {
+    float2 v[2];
+    int d[2];
+    float4 dv[IN == LV_COMPACT ? 2 : 1];
+    float cv[IN == LV_COMPACT ? 2 : 1];
+};
 
-__device__ inline RhoStage fused_stage_load(const StepArgs &a, DC &C, int zl, int x0, int y0, int ax, int ay,
-                                            bool walls)
+template <int IN>
+__device__ inline RhoStage<IN> fused_stage_load(const StepArgs &a, DC &C, int zl, int x0, int y0, int ax, int ay,
+                                                bool walls)
 {
-    RhoStage r;
+    RhoStage<IN> r;
     r.d[0] = r.d[1] = -1;
     int zp = zl;
     if (walls) {
@@ -755,7 +959,7 @@ __device__ inline RhoStage fused_stage_load(const StepArgs &a, DC &C, int zl, in
     } else {
         zp = (zl + 4 * C.nz) % C.nz;
     }
-    const float2 *src = a.rho_prev + C.node_off + (size_t)C.nx * C.ny * zp;
+    const size_t pofs = (size_t)C.node_off + (size_t)C.nx * C.ny * zp;
     const int w = ax + 2 * RH, n = w * (ay + 2 * RH);
     #pragma unroll
     for (int k = 0; k < 2; ++k) {
@@ -764,18 +968,51 @@ __device__ inline RhoStage fused_stage_load(const StepArgs &a, DC &C, int zl, in
         const int ry = e / w, rx = e - ry * w;
         // periodic wrap without branches (the region reaches RH < 4 nodes beyond the box)
         const int gx = (x0 + rx - RH + 4 * C.nx) % C.nx, gy = (y0 + ry - RH + 4 * C.ny) % C.ny;
-        r.v[k] = src[gx + C.nx * gy];
+        const size_t g = pofs + gx + (size_t)C.nx * gy;
+        r.v[k] = a.rho_prev[g];
+        if constexpr (IN == LV_COMPACT) {
+            r.dv[k] = a.dsc_prev[g];
+            r.cv[k] = a.crs_prev[g];
+        }
         r.d[k] = e0 < n ? rx + RW * ry : -1;
     }
     return r;
 }
 
-__device__ inline void fused_stage_store(float2 (*rring)[RREG], int zl, const RhoStage &r)
+template <int IN>
+__device__ inline void fused_stage_store(float2 (*rring)[RREG], float4 *dring, float *cring, int zl,
+                                         const RhoStage<IN> &r)
 {
     float2 *dst = rring[rslot(zl)];
     #pragma unroll
     for (int k = 0; k < 2; ++k)
-        if (r.d[k] >= 0) dst[r.d[k]] = r.v[k];
+        if (r.d[k] >= 0) {
+            dst[r.d[k]] = r.v[k];
+            if constexpr (IN == LV_COMPACT) {
+                dring[rslot(zl) * RREG + r.d[k]] = r.dv[k];
+                cring[rslot(zl) * RREG + r.d[k]] = r.cv[k];
+            }
+        }
+}
+
+// Loaded values of one pull in the level format IN.
+template <int ST, int IN> struct FPull;
+template <int ST> struct FPull<ST, LV_PAIR> { typename Storage<ST>::P v[Q]; };
+template <int ST> struct FPull<ST, LV_COMPACT> : CompactPull<ST> {};
+
+template <int ST, int IN, int CPP>
+__device__ inline void fpull_issue(const StepArgs &a, DC &C, const Coord &c, FPull<ST, IN> &p)
+{
+    if constexpr (IN == LV_COMPACT) pull_issue_c<ST, CPP>(a, C, c, p);
+    else pull_issue<ST, CPP>(a, C, c, p.v);
+}
+
+template <int ST, int IN, bool MV>
+__device__ inline void fpull_finish(const StepArgs &a, DC &C, const Coord &c, const WriterRing &wr, int ri,
+                                    const FPull<ST, IN> &p, NodeState &s)
+{
+    if constexpr (IN == LV_COMPACT) pull_finish_c<ST, MV>(a, C, c, wr, ri, p, s);
+    else pull_finish<ST, MV>(a, C, c, wr.r, ri, p.v, s);
 }
 
 // Position (relative to the tile origin) of entry e of the halo of width h
@@ -803,15 +1040,23 @@ __device__ inline void halo_pos(int e, int w, int nrow, int h, int ax, int ay, i
 // pull a valid node and drop the result.  On a wall layer of a case with
 // moving walls the density factor qs of Qbar goes to wq[side] for the ghost
 // layer.
-template <int ST, bool MV, int WL>
+template <int ST, bool MV, int WL, int IN>
 __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], float2 (*rring)[RREG],
-                                   float (*wq)[FREG], int zl, int zp, int x0, int y0, int ax, int ay, int h,
-                                   bool active, int tx, int ty, NodeState &s)
+                                   const float4 *dring, const float *cring, float (*wq)[FREG], int zl, int zp,
+                                   int x0, int y0, int ax, int ay, int h, bool active, int tx, int ty,
+                                   NodeState &s)
 {
     using P = typename Storage<ST>::P;
     float4 *slot = ring[fslot(zl)];
     const bool wlo = MV && C.wall == 2 && zp == 0, whi = MV && C.wall == 2 && zp == C.nz - 1;
-    const float2 *const rl[3] = {rring[rslot(zl - 1)], rring[rslot(zl)], rring[rslot(zl + 1)]};
+    WriterRing wr;
+    #pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int sl = rslot(zl - 1 + k);
+        wr.r[k] = rring[sl];
+        wr.d[k] = dring + (IN == LV_COMPACT ? sl * RREG : 0);
+        wr.c[k] = cring + (IN == LV_COMPACT ? sl * RREG : 0);
+    }
     const int w = ax + 2 * h, nrow = 2 * h * w, nh = nrow + 2 * h * ay;
     const int rot = zl & 3;
     const int e = ((int)threadIdx.x - 64 * rot + 256) & 255;
@@ -822,8 +1067,8 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         // (one memory latency instead of two, at 2 waves per SIMD)
         const int ox = min(tx, ax - 1), oy = min(ty, ay - 1);
         const Coord co = make_coord_xyz<WL>(C, x0 + ox, y0 + oy, zp);
-        P vo[Q];
-        pull_issue<ST, CP_DEFAULT>(a, C, co, vo);
+        FPull<ST, IN> vo;
+        fpull_issue<ST, IN, CP_DEFAULT>(a, C, co, vo);
         float qs;
         if (wave_halo) {
             const int eh = min(e, nh - 1);
@@ -831,17 +1076,17 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             halo_pos(eh, w, nrow, h, ax, ay, rx, ry);
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
             const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
-            P vh[Q];
-            pull_issue<ST, CP_DEFAULT>(a, C, ch, vh);
+            FPull<ST, IN> vh;
+            fpull_issue<ST, IN, CP_DEFAULT>(a, C, ch, vh);
             __builtin_amdgcn_sched_barrier(0);   // both nodes' loads issued before the first use
-            pull_finish<ST, MV>(a, C, co, rl, ridx(ox, oy), vo, s);
+            fpull_finish<ST, IN, MV>(a, C, co, wr, ridx(ox, oy), vo, s);
             if (active) {
                 slot[fidx(tx, ty)] = aux_value(C, s, qs);
                 if (wlo) wq[0][fidx(tx, ty)] = qs;
                 if (whi) wq[1][fidx(tx, ty)] = qs;
             }
             NodeState hs;
-            pull_finish<ST, MV>(a, C, ch, rl, ridx(rx, ry), vh, hs);
+            fpull_finish<ST, IN, MV>(a, C, ch, wr, ridx(rx, ry), vh, hs);
             if (e < nh) {
                 slot[fidx(rx, ry)] = aux_value(C, hs, qs);
                 if (wlo) wq[0][fidx(rx, ry)] = qs;
@@ -849,7 +1094,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             }
         } else {
             __builtin_amdgcn_sched_barrier(0);
-            pull_finish<ST, MV>(a, C, co, rl, ridx(ox, oy), vo, s);
+            fpull_finish<ST, IN, MV>(a, C, co, wr, ridx(ox, oy), vo, s);
             if (active) {
                 slot[fidx(tx, ty)] = aux_value(C, s, qs);
                 if (wlo) wq[0][fidx(tx, ty)] = qs;
@@ -862,10 +1107,10 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         float qs;
         if (active) {
             const Coord co = make_coord_xyz<WL>(C, x0 + tx, y0 + ty, zp);
-            P vo[Q];
-            pull_issue<ST, CP_DEFAULT>(a, C, co, vo);
+            FPull<ST, IN> vo;
+            fpull_issue<ST, IN, CP_DEFAULT>(a, C, co, vo);
             __builtin_amdgcn_sched_barrier(0);
-            pull_finish<ST, MV>(a, C, co, rl, ridx(tx, ty), vo, s);
+            fpull_finish<ST, IN, MV>(a, C, co, wr, ridx(tx, ty), vo, s);
             slot[fidx(tx, ty)] = aux_value(C, s, qs);
             if (wlo) wq[0][fidx(tx, ty)] = qs;
             if (whi) wq[1][fidx(tx, ty)] = qs;
@@ -875,11 +1120,11 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             halo_pos(eh, w, nrow, h, ax, ay, rx, ry);
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
             const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
-            P vh[Q];
-            pull_issue<ST, CP_DEFAULT>(a, C, ch, vh);
+            FPull<ST, IN> vh;
+            fpull_issue<ST, IN, CP_DEFAULT>(a, C, ch, vh);
             __builtin_amdgcn_sched_barrier(0);
             NodeState hs;
-            pull_finish<ST, MV>(a, C, ch, rl, ridx(rx, ry), vh, hs);
+            fpull_finish<ST, IN, MV>(a, C, ch, wr, ridx(rx, ry), vh, hs);
             slot[fidx(rx, ry)] = aux_value(C, hs, qs);
             if (wlo) wq[0][fidx(rx, ry)] = qs;
             if (whi) wq[1][fidx(rx, ry)] = qs;
@@ -934,11 +1179,15 @@ __device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int tx, int ty, 
 }
 
 // WL: WALLS_NONE or WALLS_Z (cases with walls on other axes take the two-pass step).
-template <int ST, bool MV, int WL>
+// IN, OUT: level format read and written (LV_PAIR -> LV_PAIR, or -> LV_COMPACT;
+// LV_COMPACT -> LV_COMPACT).
+template <int ST, bool MV, int WL, int IN, int OUT>
 __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
 {
     __shared__ float4 ring[FSLOTS][FREG];
     __shared__ float2 rring[4][RREG];
+    __shared__ float4 dring[IN == LV_COMPACT ? 4 * RREG : 1];
+    __shared__ float cring[IN == LV_COMPACT ? 4 * RREG : 1];
     __shared__ float wq[MV ? 2 : 1][FREG];
     const StepArgs &a = fa.a;
     const TileRange tr = tile_range(fa.nftiles);
@@ -954,18 +1203,19 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
         __syncthreads();                                   // both rings reused across tiles
         // stored densities of the planes the prologue pulls read
         for (int q = z0 - 2; q <= z0 + 1; ++q)
-            fused_stage_store(rring, q, fused_stage_load(a, C, q, x0, y0, ax, ay, walls));
+            fused_stage_store<IN>(rring, dring, cring, q, fused_stage_load<IN>(a, C, q, x0, y0, ax, ay, walls));
         __syncthreads();
         NodeState cur, nxt;
         // plane z0 (kept) and the plane below it (the top plane, for a
         // periodic z at z0 = 0); at a bottom wall the ghost layer instead
-        fused_plane<ST, MV, WL>(a, C, ring, rring, wq, z0, z0, x0, y0, ax, ay,
+        fused_plane<ST, MV, WL, IN>(a, C, ring, rring, dring, cring, wq, z0, z0, x0, y0, ax, ay,
                                 walls && (z0 == 0 || z0 == C.nz - 1) ? 2 : 1, active, tx, ty, cur);
         if (!(walls && z0 == 0))
-            fused_plane<ST, MV, WL>(a, C, ring, rring, wq, z0 - 1, z0 == 0 ? C.nz - 1 : z0 - 1, x0, y0, ax, ay, 1,
-                                    active, tx, ty, nxt);
+            fused_plane<ST, MV, WL, IN>(a, C, ring, rring, dring, cring, wq, z0 - 1, z0 == 0 ? C.nz - 1 : z0 - 1,
+                                        x0, y0, ax, ay, 1, active, tx, ty, nxt);
         __syncthreads();
-        fused_stage_store(rring, z0 + 2, fused_stage_load(a, C, z0 + 2, x0, y0, ax, ay, walls));
+        fused_stage_store<IN>(rring, dring, cring, z0 + 2,
+                              fused_stage_load<IN>(a, C, z0 + 2, x0, y0, ax, ay, walls));
         if (walls && z0 == 0) fused_ghost<MV>(C, ring, wq, 0, ax, ay);
         __syncthreads();
         // Each plane: the aux values of plane z + 1 (or the top ghost layer),
@@ -974,15 +1224,15 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
         // was last read by the pulls of plane z, before the previous barrier.
         for (int z = z0; z < z1; ++z) {
             const int zn = z + 1;
-            const RhoStage rs = fused_stage_load(a, C, z + 3, x0, y0, ax, ay, walls);
+            const RhoStage<IN> rs = fused_stage_load<IN>(a, C, z + 3, x0, y0, ax, ay, walls);
             if (walls && zn == C.nz) {
                 fused_ghost<MV>(C, ring, wq, 1, ax, ay);
             } else {
                 const int zp = zn == C.nz ? 0 : zn;        // periodic wrap
-                fused_plane<ST, MV, WL>(a, C, ring, rring, wq, zn, zp, x0, y0, ax, ay,
-                                        walls && zp == C.nz - 1 ? 2 : 1, active, tx, ty, nxt);
+                fused_plane<ST, MV, WL, IN>(a, C, ring, rring, dring, cring, wq, zn, zp, x0, y0, ax, ay,
+                                            walls && zp == C.nz - 1 ? 2 : 1, active, tx, ty, nxt);
             }
-            fused_stage_store(rring, z + 3, rs);
+            fused_stage_store<IN>(rring, dring, cring, z + 3, rs);
             __syncthreads();
             if (active) {
                 const int node = (x0 + tx) + C.nx * ((y0 + ty) + C.ny * z);
@@ -992,8 +1242,8 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
                 // back only by the next step, and the caches then keep the
                 // halo pulls of neighbouring tiles (measured +10 %); the 16-bit
                 // forms measured faster with ordinary stores
-                collide_node<ST, ST == LBCG_FP32 ? CP_STREAM : CP_DEFAULT>(a, C, node, cur, st,
-                                                                          ring[fslot(z)][fidx(tx, ty)].x);
+                collide_node<ST, ST == LBCG_FP32 ? CP_STREAM : CP_DEFAULT, OUT>(a, C, node, cur, st,
+                                                                               ring[fslot(z)][fidx(tx, ty)].x);
             }
             cur = nxt;
         }
@@ -1003,7 +1253,7 @@ __global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
 // ---------------------------------------------------------- diagnostics
 // Macroscopic fields of one case plus deterministic FP64 partial sums per
 // workgroup: {rho_R, rho_B, rho u_x, rho u_y, rho u_z, unstable-node count}.
-template <int ST>
+template <int ST, int FMT>
 __global__ __launch_bounds__(256) void k_moments(StepArgs a, int tile0, float *rR, float *rB, float *rN,
                                                  float *ux, float *uy, float *uz, double *partial)
 {
@@ -1015,7 +1265,8 @@ __global__ __launch_bounds__(256) void k_moments(StepArgs a, int tile0, float *r
     if (node < C.N) {
         const Coord c = make_coord(C, node);
         NodeState s;
-        pull_node<ST, true>(a, C, c, s);
+        if constexpr (FMT == LV_COMPACT) pull_node_c<ST, true>(a, C, c, s);
+        else pull_node<ST, true>(a, C, c, s);
         const Macro m = macro(C, s);
         if (rR) rR[node] = s.R[0];
         if (rB) rB[node] = s.R[1];
@@ -1118,13 +1369,56 @@ __device__ inline void get_dirs(const StepArgs &a, DC &C, const Coord &c, float 
     }
 }
 
-template <int ST>
+// The same from a compact level: the red share of each value rebuilt from its
+// writer's data.
+template <int ST, int I = 0>
+__device__ inline void get_dirs_c(const StepArgs &a, DC &C, const Coord &c, float *out)
+{
+    if constexpr (I < Q) {
+        using S = Storage<ST>;
+        using T = typename S::T;
+        constexpr int cl = ecls(I);
+        int src, dir;
+        pull_source<I>(C, c, src, dir);
+        const T *base = reinterpret_cast<const T *>(a.fin) + C.pop_off;
+        const size_t N = (size_t)C.N, NS = (size_t)C.NS;
+        const float2 rp = a.rho_prev[C.node_off + src];
+        float vR, vB;
+        if constexpr (I == 0) {
+            const typename S::P v = reinterpret_cast<const typename S::P *>(base)[src];
+            vR = __builtin_fmaf(rp.x, C.phi[0][0], S::dec(v.r, a.inv_scale));
+            vB = __builtin_fmaf(rp.y, C.phi[1][0], S::dec(v.b, a.inv_scale));
+        } else {
+            const bool bb = dir != I;
+            const float4 dw = a.dsc_prev[C.node_off + src];
+            const float cw = a.crs_prev[C.node_off + src];
+            const float t = S::dec(base[(size_t)(dir + 1) * NS + src], a.inv_scale);
+            const float eg = e_dot<I>(dw);
+            float seg = cl == 1 ? eg : kDiagSeg * eg;
+            if (bb) seg = -seg;
+            const float dR = __builtin_fmaf(dw.x, t, seg + (cl == 1 ? cw : 0.5f * cw));
+            vR = __builtin_fmaf(rp.x, C.phi[0][cl], dR);
+            vB = __builtin_fmaf(rp.y, C.phi[1][cl], t - dR);
+            if (C.moving && bb) {   // bounce-back at a moving wall (src is this node)
+                const float eu = wall_eu<I>(C, bounce_side<I>(c));
+                vR = __builtin_fmaf(eu * C.wg[0][cl - 1], rp.x, vR);
+                vB = __builtin_fmaf(eu * C.wg[1][cl - 1], rp.y, vB);
+            }
+        }
+        out[(size_t)I * N + c.node] = vR;
+        out[(size_t)(Q + I) * N + c.node] = vB;
+        get_dirs_c<ST, I + 1>(a, C, c, out);
+    }
+}
+
+template <int ST, int FMT>
 __global__ __launch_bounds__(256) void k_get_pop(StepArgs a, int cid, float *out)
 {
     DC &C = case_at(a.cases, cid);
     const int node = blockIdx.x * blockDim.x + threadIdx.x;
     if (node >= C.N) return;
-    get_dirs<ST>(a, C, make_coord(C, node), out);
+    if constexpr (FMT == LV_COMPACT) get_dirs_c<ST>(a, C, make_coord(C, node), out);
+    else get_dirs<ST>(a, C, make_coord(C, node), out);
 }
 
 // Equilibrium start, Eq. (18) (improved) or Eq. (6) (original), evaluated in

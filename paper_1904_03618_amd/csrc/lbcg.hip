@@ -54,6 +54,11 @@ struct lbcg_handle {
     float4 *aux = nullptr, *ghost = nullptr;
     float *wallq = nullptr;            // per ghost entry: first-layer Qbar density factor (moving walls)
     float2 *rho2[2] = {nullptr, nullptr};
+    // compact levels: the writers' recoloring data, double-buffered like rho2
+    int level = LV_PAIR;
+    float4 *dsc[2] = {nullptr, nullptr};
+    float *crs[2] = {nullptr, nullptr};
+    std::vector<uint8_t> pairlvl;      // per case: its current level is in pair format
     double *partial = nullptr, *red = nullptr;
     int64_t steps = 0, total_nodes = 0, total_pop = 0, total_ghost = 0;
     float scale = 1.0f, inv_scale = 1.0f;
@@ -73,6 +78,7 @@ struct lbcg_handle {
     int zc = 16;
     int4 *d_ftiles = nullptr;
     int nftiles = 0;
+    std::vector<int> ftile_begin, ftile_count;
     // captured step loops
     int graph_steps = 0;
     hipStream_t capture_stream = nullptr;
@@ -191,6 +197,10 @@ StepArgs args_for(const lbcg_handle *h)
     // the collision of level t records its own densities in rho2[t&1]
     a.rho_prev = h->rho2[(h->steps + 1) & 1];
     a.rho_cur = h->rho2[h->steps & 1];
+    a.dsc_prev = h->dsc[(h->steps + 1) & 1];
+    a.dsc_cur = h->dsc[h->steps & 1];
+    a.crs_prev = h->crs[(h->steps + 1) & 1];
+    a.crs_cur = h->crs[h->steps & 1];
     a.cases = h->d_cases;
     a.tiles = h->d_tiles;
     a.ntiles = h->ntiles;
@@ -231,21 +241,58 @@ int timed(lbcg_handle *h, int kernel, F &&launch)
     return LBCG_OK;
 }
 
+// Level format of case c's current level.
+int fmt_of(const lbcg_handle *h, int c)
+{
+    return h->level == LV_COMPACT && !h->pairlvl[c] ? LV_COMPACT : LV_PAIR;
+}
+
+// Call f(fmt, c0, c1) for each maximal run [c0, c1) of cases whose current
+// levels share a format (one run unless a compact handle holds a case just
+// (re)initialised in pair format).
+template <class F>
+int for_format_runs(const lbcg_handle *h, F &&f)
+{
+    for (int c0 = 0; c0 < h->ncases;) {
+        const int fmt = fmt_of(h, c0);
+        int c1 = c0 + 1;
+        while (c1 < h->ncases && fmt_of(h, c1) == fmt) ++c1;
+        const int rc = f(fmt, c0, c1);
+        if (rc) return rc;
+        c0 = c1;
+    }
+    return LBCG_OK;
+}
+
+template <int ST, int IN, int OUT>
+void launch_fused(lbcg_handle *h, hipStream_t st, const FusedArgs &fa, int grid)
+{
+    const dim3 g(grid), b(FTX * FTY);
+    if (h->moving) hipLaunchKernelGGL((k_fused<ST, true, WALLS_Z, IN, OUT>), g, b, 0, st, fa);
+    else if (h->walls == WALLS_Z) hipLaunchKernelGGL((k_fused<ST, false, WALLS_Z, IN, OUT>), g, b, 0, st, fa);
+    else hipLaunchKernelGGL((k_fused<ST, false, WALLS_NONE, IN, OUT>), g, b, 0, st, fa);
+}
+
 template <int ST>
 int launch_step(lbcg_handle *h, hipStream_t st)
 {
     StepArgs a = args_for(h);
     if (h->fused) {
-        FusedArgs fa{a, h->d_ftiles, h->nftiles, h->zc};
-        const int grid = h->persistent > 0 ? h->persistent : h->nftiles;
-        int rc = timed(h, 3, [&] {
-            const dim3 g(grid), b(FTX * FTY);
-            if (h->moving) hipLaunchKernelGGL((k_fused<ST, true, WALLS_Z>), g, b, 0, st, fa);
-            else if (h->walls == WALLS_Z) hipLaunchKernelGGL((k_fused<ST, false, WALLS_Z>), g, b, 0, st, fa);
-            else hipLaunchKernelGGL((k_fused<ST, false, WALLS_NONE>), g, b, 0, st, fa);
+        int rc = for_format_runs(h, [&](int fmt, int c0, int c1) {
+            const int t0 = h->ftile_begin[c0];
+            const int nt = h->ftile_begin[c1 - 1] + h->ftile_count[c1 - 1] - t0;
+            if (nt <= 0) return (int)LBCG_OK;
+            FusedArgs fa{a, h->d_ftiles + t0, nt, h->zc};
+            const int grid = h->persistent > 0 ? h->persistent : nt;
+            return timed(h, 3, [&] {
+                if (h->level == LV_PAIR) launch_fused<ST, LV_PAIR, LV_PAIR>(h, st, fa, grid);
+                else if (fmt == LV_PAIR) launch_fused<ST, LV_PAIR, LV_COMPACT>(h, st, fa, grid);
+                else launch_fused<ST, LV_COMPACT, LV_COMPACT>(h, st, fa, grid);
+            });
         });
         if (rc) return rc;
         HIPCHK(hipGetLastError());
+        std::fill(h->pairlvl.begin(), h->pairlvl.end(), (uint8_t)0);
         h->cur ^= 1;
         h->steps += 1;
         return LBCG_OK;
@@ -321,13 +368,27 @@ int capture_graph(lbcg_handle *h)
 }
 
 // FP64 sums over tiles [t0, t0 + nt) into h->red[0..5]; optional field exports.
+// FP64 sums over the whole cases whose tiles are [t0, t0 + nt), one launch per
+// run of cases with the same level format.
 template <int ST>
 int moments_impl(lbcg_handle *h, int t0, int nt, float *rR, float *rB, float *rN, float *ux, float *uy,
                  float *uz)
 {
     StepArgs a = args_for(h);
-    hipLaunchKernelGGL(k_moments<ST>, dim3(nt), dim3(h->block), 0, h->stream, a, t0, rR, rB, rN, ux, uy, uz,
-                       h->partial);
+    int rc = for_format_runs(h, [&](int fmt, int c0, int c1) {
+        const int r0 = std::max(t0, h->tile_begin[c0]);
+        const int r1 = std::min(t0 + nt, h->tile_begin[c1 - 1] + h->tile_count[c1 - 1]);
+        if (r1 <= r0) return (int)LBCG_OK;
+        double *part = h->partial + (size_t)6 * (r0 - t0);
+        if (fmt == LV_COMPACT)
+            hipLaunchKernelGGL((k_moments<ST, LV_COMPACT>), dim3(r1 - r0), dim3(h->block), 0, h->stream, a, r0, rR,
+                               rB, rN, ux, uy, uz, part);
+        else
+            hipLaunchKernelGGL((k_moments<ST, LV_PAIR>), dim3(r1 - r0), dim3(h->block), 0, h->stream, a, r0, rR,
+                               rB, rN, ux, uy, uz, part);
+        return (int)LBCG_OK;
+    });
+    if (rc) return rc;
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, h->stream, (const double *)h->partial, nt, h->red);
     HIPCHK(hipGetLastError());
     return LBCG_OK;
@@ -377,6 +438,10 @@ void release(lbcg_handle *h)
     (void)hipFree(h->wallq);
     (void)hipFree(h->rho2[0]);
     (void)hipFree(h->rho2[1]);
+    for (int b = 0; b < 2; ++b) {
+        (void)hipFree(h->dsc[b]);
+        (void)hipFree(h->crs[b]);
+    }
     (void)hipFree(h->partial);
     (void)hipFree(h->red);
 }
@@ -414,6 +479,7 @@ int init_case(lbcg_handle *h, int cid, const lbcg_case &c, const lbcg_fields &f)
         (void)hipFree(tmp);
     }
     if (e != hipSuccess) return fail(LBCG_EDEVICE, std::string("k_init: ") + hipGetErrorString(e));
+    h->pairlvl[cid] = 1;                     // the start level is in pair format
     return LBCG_OK;
 }
 
@@ -450,28 +516,34 @@ int check_handle(const lbcg_handle *h)
 }  // namespace
 
 // Checkpoint image: header, one descriptor per case (extents, array stride
-// and offsets, in case order), then the current level's populations of every
-// case (pop[cur]) and the writers' densities of that level (rho2[(t+1)&1]).
+// and offsets, and the format of its current level, in case order), then the
+// current level's populations of every case (pop[cur]) and the writers'
+// densities of that level (rho2[(t+1)&1]); a compact handle adds the writers'
+// recoloring data of that level (dsc, crs).
 namespace {
 struct CkptHeader {
     char magic[8];
-    int64_t version, storage, ncases, total_pop, total_nodes, steps;
+    int64_t version, storage, ncases, total_pop, total_nodes, steps, level;
 };
 struct CkptCase {
     int64_t nx, ny, nz, NS, pop_off, node_off;
+    int64_t pair_level;          // state, not layout: not compared on load
 };
 constexpr char kMagic[8] = {'L', 'B', 'C', 'G', 'C', 'K', 'P', 'T'};
-constexpr int64_t kCkptVersion = 3;
+constexpr int64_t kCkptVersion = 4;
 
-CkptCase ckpt_case(const DevCase &d)
+CkptCase ckpt_case(const lbcg_handle *h, int c)
 {
-    return CkptCase{d.nx, d.ny, d.nz, d.NS, d.pop_off, d.node_off};
+    const DevCase &d = h->dc[c];
+    return CkptCase{d.nx, d.ny, d.nz, d.NS, d.pop_off, d.node_off, h->pairlvl[c]};
 }
 
 int64_t ckpt_bytes(const lbcg_handle *h)
 {
-    return (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(CkptCase) * h->ncases + (int64_t)h->elem * h->total_pop +
-           (int64_t)sizeof(float2) * h->total_nodes;
+    int64_t b = (int64_t)sizeof(CkptHeader) + (int64_t)sizeof(CkptCase) * h->ncases +
+                (int64_t)h->elem * h->total_pop + (int64_t)sizeof(float2) * h->total_nodes;
+    if (h->level == LV_COMPACT) b += (int64_t)(sizeof(float4) + sizeof(float)) * h->total_nodes;
+    return b;
 }
 }  // namespace
 
@@ -491,6 +563,7 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     if (o.graph_steps < 0) return fail(LBCG_EINVAL, "graph_steps must be >= 0");
     if (o.kernel < LBCG_KERNEL_AUTO || o.kernel > LBCG_KERNEL_FUSED) return fail(LBCG_EINVAL, "unknown kernel");
     if (o.zchunk < 0) return fail(LBCG_EINVAL, "zchunk must be >= 0");
+    if (o.level < LBCG_LEVEL_AUTO || o.level > LBCG_LEVEL_COMPACT) return fail(LBCG_EINVAL, "unknown level format");
     if (o.storage != LBCG_FP32 && o.storage != LBCG_FP16S && o.storage != LBCG_BF16S)
         return fail(LBCG_EINVAL, "unknown storage format");
     if (o.block_nodes == 0) o.block_nodes = 256;
@@ -548,6 +621,17 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     // AUTO takes the fused step wherever it applies (measured faster than the
     // two-pass step on the benchmark boxes) and the two-pass step otherwise.
     h->fused = eligible && (o.kernel == LBCG_KERNEL_FUSED || o.kernel == LBCG_KERNEL_AUTO);
+    if (o.level == LBCG_LEVEL_COMPACT && !h->fused) {
+        delete h;
+        return fail(LBCG_EINVAL, "the compact level format needs the fused step");
+    }
+    // AUTO: the compact format for FP32 with the fused step (measured faster
+    // than pairs there); the 16-bit forms keep pairs (their compact rings
+    // leave 2 instead of 3 waves per SIMD and measured slower)
+    h->level = h->fused && (o.level == LBCG_LEVEL_COMPACT || (o.level == LBCG_LEVEL_AUTO && o.storage == LBCG_FP32))
+                   ? LV_COMPACT
+                   : LV_PAIR;
+    h->pairlvl.assign(n_cases, 1);
     h->zc = o.zchunk;
     if (h->zc == 0) {
         // default chunk: FP32 the longest of 16, 32, 64 planes that still
@@ -564,13 +648,15 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     }
     h->graph_steps = o.graph_steps + (o.graph_steps & 1);
     std::vector<int4> ftiles;
-    if (h->fused)
-        for (int c = 0; c < n_cases; ++c) {
-            const DevCase &d = h->dc[c];
+    for (int c = 0; c < n_cases; ++c) {
+        h->ftile_begin.push_back((int)ftiles.size());
+        const DevCase &d = h->dc[c];
+        if (h->fused)
             for (int z0 = 0; z0 < d.nz; z0 += h->zc)
                 for (int y0 = 0; y0 < d.ny; y0 += FTY)
                     for (int x0 = 0; x0 < d.nx; x0 += FTX) ftiles.push_back(make_int4(c, x0, y0, z0));
-        }
+        h->ftile_count.push_back((int)ftiles.size() - h->ftile_begin.back());
+    }
     h->nftiles = (int)ftiles.size();
 
     auto alloc = [&](void **p, size_t bytes) {
@@ -591,6 +677,9 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     if (ok)
         ok = alloc((void **)&h->rho2[0], sizeof(float2) * h->total_nodes) &&
              alloc((void **)&h->rho2[1], sizeof(float2) * h->total_nodes);
+    for (int b = 0; b < 2 && ok && h->level == LV_COMPACT; ++b)
+        ok = alloc((void **)&h->dsc[b], sizeof(float4) * h->total_nodes) &&
+             alloc((void **)&h->crs[b], sizeof(float) * h->total_nodes);
     if (!ok) {
         release(h);
         delete h;
@@ -610,7 +699,9 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     // keeps checkpoint images a function of the state alone
     for (int b = 0; b < 2 && rc == LBCG_OK; ++b)
         if (hipMemsetAsync(h->pop[b], 0, (size_t)h->elem * h->total_pop, h->stream) != hipSuccess ||
-            hipMemsetAsync(h->rho2[b], 0, sizeof(float2) * h->total_nodes, h->stream) != hipSuccess)
+            hipMemsetAsync(h->rho2[b], 0, sizeof(float2) * h->total_nodes, h->stream) != hipSuccess ||
+            (h->dsc[b] && hipMemsetAsync(h->dsc[b], 0, sizeof(float4) * h->total_nodes, h->stream) != hipSuccess) ||
+            (h->crs[b] && hipMemsetAsync(h->crs[b], 0, sizeof(float) * h->total_nodes, h->stream) != hipSuccess))
             rc = fail(LBCG_EDEVICE, "buffer clear failed");
     for (int c = 0; c < n_cases && rc == LBCG_OK; ++c) rc = init_any(h, c, cases[c], init[c]);
     if (rc == LBCG_OK && hipStreamSynchronize(h->stream) != hipSuccess)
@@ -636,6 +727,13 @@ int lbcg_step(lbcg_handle *h, int64_t nsteps)
     int64_t left = nsteps;
     if (h->graph_steps > 0 && !h->timing) {
         while (left > 0) {
+            if (h->level == LV_COMPACT &&
+                std::find(h->pairlvl.begin(), h->pairlvl.end(), (uint8_t)1) != h->pairlvl.end()) {
+                rc = step_once(h, h->stream);           // the converting step is not part of the graph
+                if (rc) return rc;
+                --left;
+                continue;
+            }
             if (!h->graph_exec) {
                 rc = capture_graph(h);
                 if (rc) return rc;
@@ -729,6 +827,16 @@ int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id)
 
 int32_t lbcg_storage_bytes(const lbcg_handle *h) { return live(h) ? h->elem : -1; }
 
+int32_t lbcg_step_kernel(const lbcg_handle *h)
+{
+    return live(h) ? (h->fused ? LBCG_KERNEL_FUSED : LBCG_KERNEL_TWOPASS) : -1;
+}
+
+int32_t lbcg_level_format(const lbcg_handle *h)
+{
+    return live(h) ? (h->level == LV_COMPACT ? LBCG_LEVEL_COMPACT : LBCG_LEVEL_PAIR) : -1;
+}
+
 int lbcg_timing(lbcg_handle *h, int32_t enable)
 {
     int rc = check_handle(h);
@@ -780,10 +888,20 @@ int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f)
     const int N = h->dc[case_id].N;
     StepArgs a = args_for(h);
     dim3 g((N + 255) / 256), b(256);
+    const bool cp = fmt_of(h, case_id) == LV_COMPACT;
     switch (h->storage) {
-    case LBCG_FP32: hipLaunchKernelGGL(k_get_pop<LBCG_FP32>, g, b, 0, h->stream, a, case_id, f); break;
-    case LBCG_FP16S: hipLaunchKernelGGL(k_get_pop<LBCG_FP16S>, g, b, 0, h->stream, a, case_id, f); break;
-    default: hipLaunchKernelGGL(k_get_pop<LBCG_BF16S>, g, b, 0, h->stream, a, case_id, f); break;
+    case LBCG_FP32:
+        if (cp) hipLaunchKernelGGL((k_get_pop<LBCG_FP32, LV_COMPACT>), g, b, 0, h->stream, a, case_id, f);
+        else hipLaunchKernelGGL((k_get_pop<LBCG_FP32, LV_PAIR>), g, b, 0, h->stream, a, case_id, f);
+        break;
+    case LBCG_FP16S:
+        if (cp) hipLaunchKernelGGL((k_get_pop<LBCG_FP16S, LV_COMPACT>), g, b, 0, h->stream, a, case_id, f);
+        else hipLaunchKernelGGL((k_get_pop<LBCG_FP16S, LV_PAIR>), g, b, 0, h->stream, a, case_id, f);
+        break;
+    default:
+        if (cp) hipLaunchKernelGGL((k_get_pop<LBCG_BF16S, LV_COMPACT>), g, b, 0, h->stream, a, case_id, f);
+        else hipLaunchKernelGGL((k_get_pop<LBCG_BF16S, LV_PAIR>), g, b, 0, h->stream, a, case_id, f);
+        break;
     }
     HIPCHK(hipGetLastError());
     return LBCG_OK;
@@ -808,11 +926,12 @@ int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes)
     hd.total_pop = h->total_pop;
     hd.total_nodes = h->total_nodes;
     hd.steps = h->steps;
+    hd.level = h->level;
     char *p = static_cast<char *>(host);
     std::memcpy(p, &hd, sizeof hd);
     p += sizeof hd;
     for (int c = 0; c < h->ncases; ++c) {
-        const CkptCase cc = ckpt_case(h->dc[c]);
+        const CkptCase cc = ckpt_case(h, c);
         std::memcpy(p, &cc, sizeof cc);
         p += sizeof cc;
     }
@@ -820,6 +939,12 @@ int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes)
     HIPCHK(hipMemcpy(p, h->pop[h->cur], (size_t)h->elem * h->total_pop, hipMemcpyDeviceToHost));
     p += (size_t)h->elem * h->total_pop;
     HIPCHK(hipMemcpy(p, h->rho2[(h->steps + 1) & 1], sizeof(float2) * h->total_nodes, hipMemcpyDeviceToHost));
+    p += sizeof(float2) * h->total_nodes;
+    if (h->level == LV_COMPACT) {
+        HIPCHK(hipMemcpy(p, h->dsc[(h->steps + 1) & 1], sizeof(float4) * h->total_nodes, hipMemcpyDeviceToHost));
+        p += sizeof(float4) * h->total_nodes;
+        HIPCHK(hipMemcpy(p, h->crs[(h->steps + 1) & 1], sizeof(float) * h->total_nodes, hipMemcpyDeviceToHost));
+    }
     return LBCG_OK;
 }
 
@@ -833,17 +958,20 @@ int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes)
     if (std::memcmp(hd.magic, kMagic, 8) != 0 || hd.version != kCkptVersion)
         return fail(LBCG_EINVAL, "not a checkpoint image");
     if (hd.storage != h->storage || hd.ncases != h->ncases || hd.total_pop != h->total_pop ||
-        hd.total_nodes != h->total_nodes || hd.steps < 0)
-        return fail(LBCG_EINVAL, "checkpoint of another case shape or storage format");
+        hd.total_nodes != h->total_nodes || hd.steps < 0 || hd.level != h->level)
+        return fail(LBCG_EINVAL, "checkpoint of another case shape, storage or level format");
     if (bytes < ckpt_bytes(h)) return fail(LBCG_EINVAL, "checkpoint buffer too small");
     const char *p = static_cast<const char *>(host) + sizeof hd;
+    std::vector<uint8_t> plv(h->ncases);
     for (int c = 0; c < h->ncases; ++c) {
         CkptCase cc;
         std::memcpy(&cc, p, sizeof cc);
         p += sizeof cc;
-        const CkptCase mine = ckpt_case(h->dc[c]);
-        if (std::memcmp(&cc, &mine, sizeof cc) != 0)
+        const CkptCase mine = ckpt_case(h, c);
+        if (cc.nx != mine.nx || cc.ny != mine.ny || cc.nz != mine.nz || cc.NS != mine.NS ||
+            cc.pop_off != mine.pop_off || cc.node_off != mine.node_off || (cc.pair_level & ~(int64_t)1) != 0)
             return fail(LBCG_EINVAL, "checkpoint case " + std::to_string(c) + " has other extents or layout");
+        plv[c] = (uint8_t)cc.pair_level;
     }
     HIPCHK(hipStreamSynchronize(h->stream));
     h->steps = hd.steps;
@@ -851,6 +979,13 @@ int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes)
     HIPCHK(hipMemcpy(h->pop[h->cur], p, (size_t)h->elem * h->total_pop, hipMemcpyHostToDevice));
     p += (size_t)h->elem * h->total_pop;
     HIPCHK(hipMemcpy(h->rho2[(h->steps + 1) & 1], p, sizeof(float2) * h->total_nodes, hipMemcpyHostToDevice));
+    p += sizeof(float2) * h->total_nodes;
+    if (h->level == LV_COMPACT) {
+        HIPCHK(hipMemcpy(h->dsc[(h->steps + 1) & 1], p, sizeof(float4) * h->total_nodes, hipMemcpyHostToDevice));
+        p += sizeof(float4) * h->total_nodes;
+        HIPCHK(hipMemcpy(h->crs[(h->steps + 1) & 1], p, sizeof(float) * h->total_nodes, hipMemcpyHostToDevice));
+    }
+    h->pairlvl = plv;
     return LBCG_OK;
 }
 

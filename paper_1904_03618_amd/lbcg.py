@@ -24,7 +24,7 @@ STORAGE = {"fp32": LBCG_FP32, "fp16s": LBCG_FP16S, "bf16s": LBCG_BF16S}
 EXPORTS = ("lbcg_init", "lbcg_step", "lbcg_moments", "lbcg_free", "lbcg_last_error",
            "lbcg_steps_done", "lbcg_index_map", "lbcg_get_populations", "lbcg_case_nodes",
            "lbcg_storage_bytes", "lbcg_timing", "lbcg_timing_read", "lbcg_set_fields", "lbcg_checkpoint_bytes",
-           "lbcg_checkpoint_save", "lbcg_checkpoint_load")
+           "lbcg_checkpoint_save", "lbcg_checkpoint_load", "lbcg_step_kernel", "lbcg_level_format")
 
 
 class LbcgError(RuntimeError):
@@ -55,11 +55,13 @@ class lbcg_options(C.Structure):
     _fields_ = [("storage", C.c_int32), ("diag_every", C.c_int32),
                 ("block_nodes", C.c_int32), ("persistent_blocks", C.c_int32),
                 ("kernel", C.c_int32), ("zchunk", C.c_int32),
-                ("graph_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("graph_steps", C.c_int32), ("level", C.c_int32)]
 
 
 LBCG_KERNEL_AUTO, LBCG_KERNEL_TWOPASS, LBCG_KERNEL_FUSED = 0, 1, 2
 KERNEL = {"auto": LBCG_KERNEL_AUTO, "twopass": LBCG_KERNEL_TWOPASS, "fused": LBCG_KERNEL_FUSED}
+LBCG_LEVEL_AUTO, LBCG_LEVEL_PAIR, LBCG_LEVEL_COMPACT = 0, 1, 2
+LEVEL = {"auto": LBCG_LEVEL_AUTO, "pair": LBCG_LEVEL_PAIR, "compact": LBCG_LEVEL_COMPACT}
 
 
 _lib = None
@@ -94,6 +96,9 @@ def load():
     L.lbcg_case_nodes.restype = i64
     L.lbcg_storage_bytes.argtypes = [vp]
     L.lbcg_storage_bytes.restype = i32
+    for name in ("lbcg_step_kernel", "lbcg_level_format"):
+        getattr(L, name).argtypes = [vp]
+        getattr(L, name).restype = i32
     L.lbcg_timing.argtypes = [vp, i32]
     L.lbcg_timing.restype = C.c_int
     L.lbcg_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -140,7 +145,7 @@ def _stream_ptr(stream):
 
 
 def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blocks=0, kernel="auto",
-              zchunk=0, graph_steps=0, stream=None):
+              zchunk=0, graph_steps=0, level="auto", stream=None):
     """cases: list of (params, fields) from the workload generators; fields are
     host numpy arrays (FP64).  Returns the opaque handle (an int)."""
     L = load()
@@ -162,7 +167,7 @@ def lbcg_init(cases, storage="fp32", diag_every=0, block_nodes=0, persistent_blo
     opt = lbcg_options(STORAGE[storage] if isinstance(storage, str) else int(storage),
                        int(diag_every), int(block_nodes), int(persistent_blocks),
                        KERNEL[kernel] if isinstance(kernel, str) else int(kernel), int(zchunk),
-                       int(graph_steps), 0)
+                       int(graph_steps), LEVEL[level] if isinstance(level, str) else int(level))
     h = C.c_void_p()
     _check(L.lbcg_init(carr, n, farr, C.byref(opt), C.c_void_p(_stream_ptr(stream)), C.byref(h)))
     return h.value
@@ -200,6 +205,16 @@ def lbcg_case_nodes(h, case_id):
 
 def lbcg_storage_bytes(h):
     return int(load().lbcg_storage_bytes(C.c_void_p(h)))
+
+
+def lbcg_step_kernel(h):
+    """'fused' or 'twopass': the step kernel the handle resolved at init."""
+    return {LBCG_KERNEL_FUSED: "fused", LBCG_KERNEL_TWOPASS: "twopass"}[int(load().lbcg_step_kernel(C.c_void_p(h)))]
+
+
+def lbcg_level_format(h):
+    """'pair' or 'compact': the level format the handle resolved at init."""
+    return {LBCG_LEVEL_PAIR: "pair", LBCG_LEVEL_COMPACT: "compact"}[int(load().lbcg_level_format(C.c_void_p(h)))]
 
 
 def lbcg_set_fields(h, case_id, rhoR, rhoB, ux, uy, uz):

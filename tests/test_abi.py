@@ -129,6 +129,14 @@ def test_init_rejects_bad_options_and_pointers():
     assert rc == B.LBCG_EINVAL and "zchunk" in B.lbcg_last_error()
     rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 0, 0, -1, 0))
     assert rc == B.LBCG_EINVAL and "graph_steps" in B.lbcg_last_error()
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, 0, 0, 0, 3))
+    assert rc == B.LBCG_EINVAL and "level" in B.lbcg_last_error()
+    # the compact level format exists only with the fused step
+    rc, _ = _init_rc(p, opt=B.lbcg_options(0, 0, 0, 0, B.LBCG_KERNEL_TWOPASS, 0, 0, B.LBCG_LEVEL_COMPACT))
+    assert rc == B.LBCG_EINVAL and "compact" in B.lbcg_last_error()
+    pw = dict(p, bc=(0, 1, 0))
+    rc, _ = _init_rc(pw, opt=B.lbcg_options(0, 0, 0, 0, B.LBCG_KERNEL_AUTO, 0, 0, B.LBCG_LEVEL_COMPACT))
+    assert rc == B.LBCG_EINVAL and "compact" in B.lbcg_last_error()
     L = B.load()
     h = C.c_void_p()
     assert L.lbcg_init(None, 1, None, None, None, C.byref(h)) == B.LBCG_EINVAL
@@ -173,3 +181,4 @@ def test_never_issued_handle_is_rejected_without_being_read():
     assert L.lbcg_free(bogus) == B.LBCG_ESTATE
     assert L.lbcg_steps_done(bogus) == -1 and L.lbcg_case_nodes(bogus, 0) == -1
     assert L.lbcg_storage_bytes(bogus) == -1 and L.lbcg_checkpoint_bytes(bogus) == -1
+    assert L.lbcg_step_kernel(bogus) == -1 and L.lbcg_level_format(bogus) == -1

@@ -304,14 +304,91 @@ def _fused_cases():
     }
 
 
+_ORACLE_CACHE = {}
+
+
+def _cached_oracle(name, p, fl, steps):
+    if name not in _ORACLE_CACHE:
+        _ORACLE_CACHE[name] = oracle_run(p, fl, steps)
+    return _ORACLE_CACHE[name]
+
+
+@pytest.mark.parametrize("level", ["pair", "compact"])
 @pytest.mark.parametrize("name", list(_fused_cases()))
-def test_fused_kernel_matches_oracle(name):
+def test_fused_kernel_matches_oracle(name, level):
     """The fused single-pass step against the FP64 oracle at the standard
-    tolerances."""
+    tolerances, with levels stored as colour pairs and in the compact format
+    (totals plus the writers' recoloring data, Eq. 10-11)."""
     maker, zchunk, steps = _fused_cases()[name]
     p, fl = maker()
-    g = gpu_run([(p, fl)], steps, kernel="fused", zchunk=zchunk)[0]
-    assert_parity(f"fused_{name}", g, oracle_run(p, fl, steps), p)
+    g = gpu_run([(p, fl)], steps, kernel="fused", zchunk=zchunk, level=level)[0]
+    assert_parity(f"fused_{level}_{name}", g, _cached_oracle(name, p, fl, steps), p)
+
+
+@pytest.mark.parametrize("storage,tn,tu", [("fp16s", 6e-3, 2e-4), ("bf16s", 1e-1, 2e-3)])
+def test_compact_levels_in_16bit_forms(storage, tn, tu):
+    """The compact level format with 16-bit totals against the oracle, at the
+    bounds of the 16-bit pair forms."""
+    p, fl = W.random_state_case(20, 18, 12, seed=47, bc=(0, 0, 1), theta=(70.0, 110.0), force=(1e-5, 0, 0))
+    g = gpu_run([(p, fl)], 500, storage=storage, kernel="fused", zchunk=5, level="compact")[0]
+    e = max_err(g, _cached_oracle("shifted_storage_47", p, fl, 500))
+    report(f"compact_{storage}", e)
+    assert e["rhoN"] <= tn and max(e["ux"], e["uy"], e["uz"]) <= tu
+
+
+def test_auto_resolves_kernel_and_level():
+    """Default options: the fused step wherever the walls allow it, compact
+    levels for FP32 there, pairs for the 16-bit forms and the two-pass step."""
+    from paper_1904_03618_amd import lbcg as B
+    zc = W.random_state_case(9, 8, 7, seed=91, bc=(0, 0, 1))
+    yc = W.random_state_case(9, 8, 7, seed=92, bc=(0, 1, 0))
+    for cases, storage, want in (([zc], "fp32", ("fused", "compact")), ([zc], "fp16s", ("fused", "pair")),
+                                 ([zc, yc], "fp32", ("twopass", "pair"))):
+        h = B.lbcg_init(cases, storage=storage)
+        try:
+            assert (B.lbcg_step_kernel(h), B.lbcg_level_format(h)) == want, (storage, len(cases))
+        finally:
+            B.lbcg_free(h)
+
+
+def test_compact_handle_with_a_reinitialised_case():
+    """In a compact handle, lbcg_set_fields puts one case back to a pair-format
+    start level while the other stays compact: the next step runs the two
+    formats in separate launches, and each case equals its own handle (the
+    untouched case run without interruption, the reset case run from a fresh
+    init) bit for bit, through graph replays and a checkpoint taken right
+    after the reset."""
+    import torch
+    from paper_1904_03618_amd import lbcg as B
+    c0 = W.random_state_case(13, 11, 10, seed=81, bc=(0, 0, 1), theta=(70.0, 120.0))
+    c1 = W.random_state_case(10, 12, 9, seed=82)
+    p1b, fl1b = W.random_state_case(10, 12, 9, seed=83)
+    h = B.lbcg_init([c0, c1], graph_steps=4, level="compact")
+    h0 = B.lbcg_init([c0], level="compact")
+    h1 = B.lbcg_init([(p1b, fl1b)], level="compact")
+    hk = B.lbcg_init([c0, c1], level="compact")
+    try:
+        B.lbcg_step(h, 11)
+        B.lbcg_step(h0, 11)
+        dev = [torch.tensor(fl1b[k]).cuda() for k in ("rhoR", "rhoB", "ux", "uy", "uz")]
+        B.lbcg_set_fields(h, 1, *dev)
+        img = B.lbcg_checkpoint_save(h)
+        B.lbcg_checkpoint_load(hk, img)
+        for n in (1, 8, 5):
+            for hh in (h, hk):
+                B.lbcg_step(hh, n)
+            B.lbcg_step(h0, n)
+            B.lbcg_step(h1, n)
+            for hh in (h, hk):
+                a0 = B.lbcg_get_populations(hh, 0).cpu().numpy()
+                a1 = B.lbcg_get_populations(hh, 1).cpu().numpy()
+                b0 = B.lbcg_get_populations(h0, 0).cpu().numpy()
+                b1 = B.lbcg_get_populations(h1, 0).cpu().numpy()
+                torch.cuda.synchronize()
+                assert np.array_equal(a0, b0) and np.array_equal(a1, b1), n
+    finally:
+        for hh in (h, h0, h1, hk):
+            B.lbcg_free(hh)
 
 
 def test_fused_batch_equals_single_runs():
@@ -360,9 +437,8 @@ def test_fused_shifted_storage(storage, tn, tu):
     """The fused step in the 16-bit storage forms against the oracle, at the
     bounds the two-pass step is held to."""
     p, fl = W.random_state_case(20, 18, 12, seed=47, bc=(0, 0, 1), theta=(70.0, 110.0), force=(1e-5, 0, 0))
-    g = gpu_run([(p, fl)], 500, storage=storage, kernel="fused", zchunk=5)[0]
-    o = oracle_run(p, fl, 500)
-    e = max_err(g, o)
+    g = gpu_run([(p, fl)], 500, storage=storage, kernel="fused", zchunk=5, level="pair")[0]
+    e = max_err(g, _cached_oracle("shifted_storage_47", p, fl, 500))
     report(f"fused_{storage}", e)
     assert e["rhoN"] <= tn and max(e["ux"], e["uy"], e["uz"]) <= tu
 

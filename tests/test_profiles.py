@@ -1,7 +1,8 @@
-"""The committed profile summaries describe the current kernels: the HBM
+"""The committed measurement artefacts describe the current code: the HBM
 traffic figures that the benchmark reports were taken on the same step-kernel
-source (a source hash recorded with them), and every summary names the
-command that produced it."""
+source (a source hash recorded with them), every profile summary names the
+command that produced it, and the stored full-size oracle samples were made by
+the current oracle."""
 import glob
 import json
 import os
@@ -28,3 +29,20 @@ def test_every_summary_names_its_command():
         with open(path) as fh:
             text = fh.read()
         assert "rocprofv3 " in text, path
+
+
+def test_full_size_goldens_match_the_oracle_and_inputs():
+    """The stored full-size oracle samples were computed by the current oracle
+    source; each holds its inputs' digest and its sample of nodes."""
+    import hashlib
+
+    import numpy as np
+
+    import full_size_cases as FS
+    with open(os.path.join(ROOT, "oracle", "lbcg_oracle.c"), "rb") as fh:
+        od = hashlib.sha256(fh.read()).hexdigest()[:16]
+    for name, (maker, steps) in FS.CASES.items():
+        g = np.load(os.path.join(ROOT, "tests", "golden", name + ".npz"))
+        assert str(g["oracle_digest"]) == od, f"{name}: made by another oracle; rerun tests/golden/make_full_size.py"
+        assert int(g["steps"]) == steps
+        assert g["idx"].size >= 2000 and all(g[k].shape == g["idx"].shape for k in ("rhoN", "ux"))
