@@ -1062,9 +1062,9 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
     const int e = ((int)threadIdx.x - 64 * rot + 256) & 255;
     const int wave = (int)threadIdx.x >> 6;
     const bool wave_halo = __builtin_amdgcn_readfirstlane((((wave - rot) & 3) * 64 < nh) ? 1 : 0) != 0;
-    if constexpr (sizeof(P) == 8) {
-        // FP32: a wave with halo duty issues both nodes' loads before it waits
-        // (one memory latency instead of two, at 2 waves per SIMD)
+    if constexpr (sizeof(P) == 8 && IN == LV_PAIR) {
+        // FP32 pairs: a wave with halo duty issues both nodes' loads before it
+        // waits (one memory latency instead of two, at 2 waves per SIMD)
         const int ox = min(tx, ax - 1), oy = min(ty, ay - 1);
         const Coord co = make_coord_xyz<WL>(C, x0 + ox, y0 + oy, zp);
         FPull<ST, IN> vo;
@@ -1102,8 +1102,9 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             }
         }
     } else {
-        // 16-bit forms: the own node, then the halo node; fewer registers
-        // (3 waves per SIMD), measured faster for these forms
+        // 16-bit forms and compact levels: the own node, then the halo node;
+        // fewer registers (3 waves per SIMD for the 16-bit pairs), measured
+        // faster for these forms
         float qs;
         if (active) {
             const Coord co = make_coord_xyz<WL>(C, x0 + tx, y0 + ty, zp);

@@ -188,7 +188,7 @@ __device__ inline unsigned xcd_contiguous(unsigned lin, unsigned n)
     return x * q + min(x, r) + l;
 }
 
-template <int NO, int ZW, int CT>
+template <int NO, int ZW, int CT, bool DYR>
 __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__restrict__ W,
                                                      const float *__restrict__ bias, int pmask, int relu, sg_view y,
                                                      sg_view y32, int accumulate)
@@ -263,6 +263,65 @@ __global__ __launch_bounds__(256) void k_conv3_brick(sg_view x, const bf16 *__re
         for (int k = 0; k < PER; ++k)
             if (hdst[k] >= 0) *reinterpret_cast<bf16x8 *>(&halo[hdst[k]]) = hv[k];
         __syncthreads();
+        if constexpr (DYR) {
+            // The three dy taps of a (dz, dx, channel group) read the same
+            // halo rows shifted by one: a lane loads the 6 rows its 4 output
+            // rows need once and feeds them to three K blocks (dy = -1, 0, 1),
+            // half the LDS fragment reads of one read per MFMA row and tap.
+            // Super-block s gives lane group grp the combination q = 4 s + grp
+            // of (dz, dx, c8); combinations past the last get zero weights.
+            const int Q9 = 9 * gpt, nsb = (Q9 + 3) >> 2, lg = lgp;
+            auto rows = [&](int s, bf16x8 (&R)[ZW][6]) {
+                const int q = min(4 * s + grp, Q9 - 1);
+                const int c8 = q & (gpt - 1), dzx = q >> lg;
+                const int dz = dzx / 3, dx = dzx % 3;                 // 0..2: offsets + 1
+                const int hx = col + dx;
+                #pragma unroll
+                for (int z = 0; z < ZW; ++z)
+                    #pragma unroll
+                    for (int r = 0; r < 6; ++r) {
+                        const int hp = ((wave * ZW + z + dz) * HY + r) * HX + hx;
+                        R[z][r] = *reinterpret_cast<const bf16x8 *>(&halo[hp * LROW + 8 * swz(hx, c8)]);
+                    }
+            };
+            auto wts = [&](int s, bf16x8 (&A)[3][NO]) {
+                const int q4 = 4 * s + grp, q = min(q4, Q9 - 1);
+                const int c8 = q & (gpt - 1), dzx = q >> lg;
+                const int dz = dzx / 3, dx = dzx % 3;
+                #pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const int tap = dz * 9 + d * 3 + dx;
+                    #pragma unroll
+                    for (int o = 0; o < NO; ++o) {
+                        const bf16x8 v = *reinterpret_cast<const bf16x8 *>(wrow + (int64_t)16 * o * K + tap * ci + c0 + 8 * c8);
+                        A[d][o] = q4 < Q9 ? v : zero;
+                    }
+                }
+            };
+            auto mma3 = [&](const bf16x8 (&R)[ZW][6], const bf16x8 (&A)[3][NO]) {
+                #pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    #pragma unroll
+                    for (int o = 0; o < NO; ++o)
+                        #pragma unroll
+                        for (int i = 0; i < NF; ++i) acc[o][i] = mfma(A[d][o], R[i / 4][i % 4 + d], acc[o][i]);
+            };
+            bf16x8 R0[ZW][6], R1[ZW][6], A0[3][NO], A1[3][NO];
+            rows(0, R0);
+            wts(0, A0);
+            int s = 0;
+            for (; s + 2 <= nsb; s += 2) {
+                rows(s + 1, R1);
+                wts(s + 1, A1);
+                mma3(R0, A0);
+                const int sn = min(s + 2, nsb - 1);
+                rows(sn, R0);
+                wts(sn, A0);
+                mma3(R1, A1);
+            }
+            if (s < nsb) mma3(R0, A0);
+            continue;
+        }
         // K blocks of 4 (tap, 8-channel group) pairs.  The full blocks run
         // unmasked; a last partial block (27 gpt not a multiple of 4) zeroes
         // the weights of its idle lanes.
@@ -357,8 +416,13 @@ static void launch_brick(const sg_view *x, const void *w, const float *bias, int
                          const sg_view &y, const sg_view &y32, int accumulate, hipStream_t st)
 {
     const unsigned nb = (unsigned)((int64_t)x->n * (x->d / (4 * ZW)) * (x->h / BY) * (x->w / BX));
-    hipLaunchKernelGGL((k_conv3_brick<NO, ZW, CT>), dim3(nb, co / (16 * NO)), dim3(256), 0, st, *x, (const bf16 *)w,
-                       bias, pmask, relu, y, y32, accumulate);
+    // row reuse across the dy taps where it measured faster: one output block
+    // (the full-resolution 16-channel layers: 364 -> 321 us on the 128 x 128 x
+    // 512 box) and one-plane 32-channel chunks; the two-plane two-block forms
+    // need 156-164 registers for it and lose occupancy (102 -> 143 us)
+    constexpr bool dyr = NO == 1 || (ZW == 1 && CT == 32);
+    hipLaunchKernelGGL((k_conv3_brick<NO, ZW, CT, dyr>), dim3(nb, co / (16 * NO)), dim3(256), 0, st, *x,
+                       (const bf16 *)w, bias, pmask, relu, y, y32, accumulate);
 }
 
 // 1x1x1 convolution with few outputs (the network head): one position per

@@ -266,7 +266,7 @@ def hybrid(net, p, fl, every, t_start, t_end, heal=20, gate=1.0, trust=3, skill=
 
 def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, val_amp=0.045,
                iters=3000, segments=6, heal=20, rec=20, batch=4, slab=None, t_start=None, lr=1e-3, lr_min=1e-5,
-               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), trust=3, skill=0.5, log=None):
+               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), trust=3, skill=0.5, trust_sweep=(), log=None):
     """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
     steps apart from snapshots every `rec` steps) in `segments` pieces of one
     cosine schedule, once per seed (initial weights and pair sampling); after
@@ -274,7 +274,9 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
     neither trained on nor evaluated) and the best weights over all seeds and
     pieces by `score` are kept.  On the held-out amplitude eval_amp, run the
     gated hybrid at each gate, the same gate with persistence in place of the
-    network, and the plain LB run.  Returns a summary."""
+    network, and the plain LB run; for each value in trust_sweep, the hybrid
+    at the first gate with that many jumps per passed check.  Returns a
+    summary."""
     import math
     import torch
     steps = steps if steps is not None else int(4.5 * math.sqrt(L / 2e-5)) // every * every
@@ -356,6 +358,15 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
                 f"{hyb['jumps_within_gate']} within the gate, largest jump error {hyb['max_jump_error']:.3f}, "
                 f"final front error {hyb['final_front_error']:.3f}, gain {lb / hyb['wall_s']:.2f}; persistence "
                 f"{per['jumps']} jumps, final {per['final_front_error']:.3f}")
+    for tr in trust_sweep:
+        h = hybrid(full, p, fl, every, t_start, steps, heal=heal, gate=gates[0], trust=tr, skill=skill, ref_fronts=ref)
+        res.setdefault("trust_sweep", {})[str(tr)] = dict(
+            gain=lb / h["wall_s"], jumps=h["jumps"], checks=h["checks_run"], checks_passed=h["checks_passed"],
+            jumps_within_gate=h["jumps_within_gate"], max_jump_error=h["max_jump_error"],
+            final_front_error=h["final_front_error"])
+        if log:
+            log(f"trust {tr}: {h['jumps']} jumps, {h['jumps_within_gate']} within the gate, final front error "
+                f"{h['final_front_error']:.3f}, gain {lb / h['wall_s']:.2f}")
     return res
 
 
@@ -388,11 +399,13 @@ def main(argv=None):
     ap.add_argument("--trust", type=int, default=3, help="jumps after each passed check")
     ap.add_argument("--skill", type=float, default=0.5, help="largest phase-field error of a passed check, "
                                                             "relative to the change over the interval")
+    ap.add_argument("--trust-sweep", default="", help="further jumps-per-check values to evaluate, e.g. 1,2")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
     res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, rec=a.rec, slab=a.slab or None,
                      segments=a.segments, seeds=tuple(int(v) for v in a.seeds.split(",")), trust=a.trust,
-                     skill=a.skill, log=lambda m: print(m, flush=True))
+                     skill=a.skill,
+                     trust_sweep=tuple(int(v) for v in a.trust_sweep.split(",") if v), log=lambda m: print(m, flush=True))
     txt = json.dumps(res)
     print(txt, flush=True)
     if a.out:
