@@ -386,6 +386,13 @@ def test_compact_handle_with_a_reinitialised_case():
                 b1 = B.lbcg_get_populations(h1, 0).cpu().numpy()
                 torch.cuda.synchronize()
                 assert np.array_equal(a0, b0) and np.array_equal(a1, b1), n
+        # a compact image does not load into a pair-level handle of the same boxes
+        hp = B.lbcg_init([c0, c1], level="pair")
+        try:
+            with pytest.raises(B.LbcgError):
+                B.lbcg_checkpoint_load(hp, img)
+        finally:
+            B.lbcg_free(hp)
     finally:
         for hh in (h, h0, h1, hk):
             B.lbcg_free(hh)
