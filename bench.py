@@ -46,10 +46,16 @@ KERNEL_INDEX = {"aux": "k_aux", "ghost": "k_ghost", "collide": "k_collide", "fus
 
 
 def kernel_source_hash():
+    """Hash of the step kernels' code (comments and blank lines left out, so
+    that a comment edit does not invalidate a counter profile)."""
+    import re
     h = hashlib.sha256()
     for f in ("kernels.hpp", "d3q19.hpp"):
-        with open(os.path.join(ROOT, "paper_1904_03618_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_03618_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).rstrip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

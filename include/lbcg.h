@@ -224,14 +224,16 @@ int64_t lbcg_steps_done(const lbcg_handle *h);
 int lbcg_index_map(lbcg_handle *h, int32_t case_id, int64_t *src_node, int8_t *src_dir);
 
 /* Decoded FP32 populations of case case_id at the current level into
- * caller-owned DEVICE memory f[(k*19 + i)*N + node].  Errors as above. */
+ * caller-owned DEVICE memory f[(k*19 + i)*N + node] (with compact levels the
+ * red and blue shares are rebuilt from the writers' data exactly as the next
+ * step rebuilds them).  Errors as above. */
 int lbcg_get_populations(lbcg_handle *h, int32_t case_id, float *f);
 
 /* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
  * recording an event pair around every kernel of every following step
  * (enable = 0 stops).  lbcg_timing_read synchronises the stream and writes,
  * for the kernels {moments pass, wall ghost layer, collision pass, fused
- * step}, the summed duration in milliseconds into ms[4] and the number of
+ * step} (a handle on the fused step records only the last), the summed duration in milliseconds into ms[4] and the number of
  * recorded launches into launches[4]; it then clears the totals.  Errors: LBCG_ESTATE,
  * LBCG_EINVAL (NULL output), LBCG_EDEVICE. */
 int lbcg_timing(lbcg_handle *h, int32_t enable);
@@ -248,9 +250,10 @@ int32_t lbcg_level_format(const lbcg_handle *h);
 
 /* Checkpoint / resume.  The state of a handle at its current level is the
  * stored population values of every case (raw bits, storage format of the
- * handle), the colour densities their writers stored with them, and the
- * step count; everything else (aux and ghost layers) is recomputed by the
- * next step.  lbcg_checkpoint_bytes gives the size of that image (-1 for a
+ * handle), the colour densities their writers stored with them (with compact
+ * levels also the writers' recoloring data and, per case, whether its level
+ * is still a pair-format start level), and the step count; everything else
+ * (aux and ghost layers) is recomputed by the next step.  lbcg_checkpoint_bytes gives the size of that image (-1 for a
  * bad handle).  lbcg_checkpoint_save synchronises the handle's stream and
  * copies the image into caller-owned HOST memory of at least that size.
  * lbcg_checkpoint_load restores an image into a handle created with the same
@@ -259,7 +262,7 @@ int32_t lbcg_level_format(const lbcg_handle *h);
  * parameters other than the shapes are the handle's own); the next steps then
  * continue bit for bit as the saved handle would have.  Errors: LBCG_ESTATE,
  * LBCG_EINVAL (NULL buffer, too small, or an image of other case extents,
- * case order or storage format), LBCG_EDEVICE. */
+ * case order, storage or level format), LBCG_EDEVICE. */
 int64_t lbcg_checkpoint_bytes(const lbcg_handle *h);
 int lbcg_checkpoint_save(lbcg_handle *h, void *host, int64_t bytes);
 int lbcg_checkpoint_load(lbcg_handle *h, const void *host, int64_t bytes);

@@ -1,7 +1,9 @@
 // kernels.hpp -- gfx950 kernels of one time step of the improved 3D
 // colour-gradient MRT lattice Boltzmann model (Wen, Li, Yu & Luo).
 //
-// One step at level t is three launches over all tiles of all cases:
+// A step at level t is either one launch of k_fused (below: z-marching
+// tiles, the phase-field halo in LDS; cases with walls, if any, on z), or the
+// two-pass form, three launches over all tiles of all cases:
 //   k_aux     pull the 38 populations, moments (Eq. 4), phase field rho^N
 //             (text after Eq. 8) and Qbar = u sum_k rho_k (1 - 3 c_s^k^2)
 //             (Eq. 46-49) -> aux
@@ -19,7 +21,10 @@
 // colour's h terms, and g_i = f_i - sum_k R_k phi_i^k; the rest state is
 // isotropic, so its moments are known in closed form and never rounded.
 // The colour gradient at level t needs the level-t densities of all 18
-// neighbours, so the moments pass must finish before the collision pass.
+// neighbours, so in the two-pass form the moments pass must finish before the
+// collision pass.  Levels are stored as colour pairs or, with the fused step,
+// in the compact format of d3q19.hpp (totals plus the writers' recoloring
+// data).
 #pragma once
 
 #include "d3q19.hpp"
