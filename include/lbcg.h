@@ -110,7 +110,7 @@ typedef struct lbcg_fields {
 /* Step kernels. */
 #define LBCG_KERNEL_AUTO 0      /* the fused step when every case allows it, else two-pass */
 #define LBCG_KERNEL_TWOPASS 1   /* moments pass + collision pass (any boundaries) */
-#define LBCG_KERNEL_FUSED 2     /* single pass, z-marching 16 x 16 tiles with the
+#define LBCG_KERNEL_FUSED 2     /* single pass, z-marching 32 x 8 tiles with the
                                    phase-field halo in LDS; eligible cases: no
                                    walls, or walls on the z axis (any contact
                                    angle, at rest or moving) */
@@ -133,9 +133,9 @@ typedef struct lbcg_fields {
  * the two-pass kernels (0 = default 256; 64, 128, 192 or 256).
  * persistent_blocks: 0 = one workgroup per tile, >0 = that many workgroups
  * looping over all tiles of all cases (batched persistent launch).
- * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default: 16
- * for the 16-bit forms; for FP32 the longest of 16, 32, 64 that leaves at
- * least 512 tiles).
+ * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default: the
+ * longest of 16, 32, 64, 128 that leaves at least 512 tiles for FP32, of 16,
+ * 32, 64 that leaves at least 2048 tiles for the 16-bit forms, else 16).
  * graph_steps: 0 = launch every kernel of every step; n > 0 = capture n steps
  * (rounded up to even) once into a HIP graph and replay it; with diag_every
  * the stability check then runs at the first replay boundary at or after each

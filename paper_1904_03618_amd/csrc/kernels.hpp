@@ -246,8 +246,13 @@ __device__ inline void pull_all(const StepArgs &a, DC &C, const Coord &c, const 
 // stored-density planes z-1, z, z+1 (rl[0..2], row length RW; ri: the node's
 // index in a plane) instead of from memory.  A bounce-back lane takes its own
 // density (its slot read is discarded), as the memory form does.
-constexpr int RH = 3;                    // halo of the stored-density planes around a fused tile
-constexpr int RW = 16 + 2 * RH, RREG = RW * RW;
+// Fused tiles are FTX x FTY columns: 32 x 8, so that a tile row of 4-byte
+// values fills one 128-byte cache line (a wave's load touches 2 lines, where
+// 16 x 16 tiles touched 4 half lines) and only 2 x 8 of the halo lies in
+// strided columns.
+constexpr int FTX = 32, FTY = 8;
+constexpr int RH = 2;                    // halo of the stored-density planes around a fused tile
+constexpr int RW = FTX + 2 * RH, RREG = RW * (FTY + 2 * RH);
 
 // Issue phase: the 19 population loads of a node, all in flight at once.
 template <int ST, int CPP, int I = 0>
@@ -910,7 +915,6 @@ __global__ __launch_bounds__(256) void k_collide(StepArgs a)
 // pulled with a two-node halo.  The four ring slots let one barrier per plane
 // suffice: the slot written for plane z + 2 was last read by the collision of
 // plane z - 2, which every lane finished before the previous barrier.
-constexpr int FTX = 16, FTY = 16;
 constexpr int FH = 2;                                  // halo width the ring can hold
 constexpr int FRX = FTX + 2 * FH, FRY = FTY + 2 * FH, FREG = FRX * FRY;
 constexpr int FSLOTS = 4;
@@ -964,6 +968,7 @@ __device__ inline RhoStage<IN> fused_stage_load(const StepArgs &a, DC &C, int zl
     } else {
         zp = (zl + 4 * C.nz) % C.nz;
     }
+    static_assert(RREG <= 512, "the writers' region must fit two rounds of 256 lanes");
     const size_t pofs = (size_t)C.node_off + (size_t)C.nx * C.ny * zp;
     const int w = ax + 2 * RH, n = w * (ay + 2 * RH);
     #pragma unroll
@@ -1036,6 +1041,47 @@ __device__ inline void halo_pos(int e, int w, int nrow, int h, int ax, int ay, i
     }
 }
 
+// Position (relative to the tile origin) of entry e of the ring at distance
+// exactly 2 around an ax x ay tile: the rows y = -2 and y = ay + 1 (ax + 4
+// wide), then the columns x = -2 and x = ax + 1 (y = -1 .. ay).
+__device__ inline void ring2_pos(int e, int ax, int ay, int &rx, int &ry)
+{
+    const int w = ax + 4;
+    if (e < 2 * w) {
+        const int r = e >= w;
+        rx = e - r * w - 2;
+        ry = r ? ay + 1 : -2;
+    } else {
+        const int e1 = e - 2 * w, r = e1 >= ay + 2;
+        ry = e1 - r * (ay + 2) - 1;
+        rx = r ? ax + 1 : -2;
+    }
+}
+
+// The second halo ring of a wall layer (needed by the ghost layer's in-plane
+// gradient): its writers lie beyond the LDS rings (RH = 2 nodes around the
+// tile), so these pulls read the writers' words from memory (two planes per
+// column of tiles).
+template <int ST, bool MV, int WL, int IN>
+__device__ inline void fused_ring2(const StepArgs &a, DC &C, float4 *slot, float (*wq)[FREG], bool wlo, bool whi,
+                                   int zp, int x0, int y0, int ax, int ay)
+{
+    const int n = 2 * (ax + 4) + 2 * (ay + 2);
+    for (int e = (int)threadIdx.x; e < n; e += 256) {
+        int rx, ry;
+        ring2_pos(e, ax, ay, rx, ry);
+        const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
+        const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
+        NodeState hs;
+        if constexpr (IN == LV_COMPACT) pull_node_c<ST, MV>(a, C, ch, hs);
+        else pull_node<ST, MV, CP_DEFAULT>(a, C, ch, hs);
+        float qs;
+        slot[fidx(rx, ry)] = aux_value(C, hs, qs);
+        if (wlo) wq[0][fidx(rx, ry)] = qs;
+        if (whi) wq[1][fidx(rx, ry)] = qs;
+    }
+}
+
 // Aux values of plane zp (0 <= zp < nz) into the ring slot of plane zl (zl =
 // zp, or zp -+ nz for the periodic neighbours of the chunk's end planes): the
 // lane's own node (pulled state kept in s) and the halo of width h (1, or 2
@@ -1062,7 +1108,8 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         wr.d[k] = dring + (IN == LV_COMPACT ? sl * RREG : 0);
         wr.c[k] = cring + (IN == LV_COMPACT ? sl * RREG : 0);
     }
-    const int w = ax + 2 * h, nrow = 2 * h * w, nh = nrow + 2 * h * ay;
+    // the one-node ring here; a wall layer's second ring after it (fused_ring2)
+    const int w = ax + 2, nrow = 2 * w, nh = nrow + 2 * ay;
     const int rot = zl & 3;
     const int e = ((int)threadIdx.x - 64 * rot + 256) & 255;
     const int wave = (int)threadIdx.x >> 6;
@@ -1078,7 +1125,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         if (wave_halo) {
             const int eh = min(e, nh - 1);
             int rx, ry;
-            halo_pos(eh, w, nrow, h, ax, ay, rx, ry);
+            halo_pos(eh, w, nrow, 1, ax, ay, rx, ry);
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
             const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
             FPull<ST, IN> vh;
@@ -1123,7 +1170,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         }
         for (int eh = e; eh < nh; eh += 256) {
             int rx, ry;
-            halo_pos(eh, w, nrow, h, ax, ay, rx, ry);
+            halo_pos(eh, w, nrow, 1, ax, ay, rx, ry);
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
             const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
             FPull<ST, IN> vh;
@@ -1136,6 +1183,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             if (whi) wq[1][fidx(rx, ry)] = qs;
         }
     }
+    if (h == 2) fused_ring2<ST, MV, WL, IN>(a, C, slot, wq, wlo, whi, zp, x0, y0, ax, ay);
 }
 
 // Ghost layer beyond the wall at side `side` (0: z = -1, 1: z = nz) over the

@@ -634,17 +634,20 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
     h->pairlvl.assign(n_cases, 1);
     h->zc = o.zchunk;
     if (h->zc == 0) {
-        // default chunk: FP32 the longest of 16, 32, 64 planes that still
-        // leaves at least 512 tiles (two per CU); 16-bit forms 16 planes
-        // (measured best on the 128^3 and 128 x 128 x 512 boxes)
+        // default chunk: the longest of 16 .. 128 planes (FP32) or 16 .. 64
+        // planes (16-bit forms) that still leaves at least 512 tiles (FP32: two
+        // workgroups per CU) or 2048 tiles (16-bit forms: three per CU over
+        // several rounds); measured best or within 2 % on the 128^3,
+        // 128 x 128 x 512 and 256 x 256 x 1024 boxes
         h->zc = 16;
-        if (o.storage == LBCG_FP32)
-            for (int zc : {32, 64}) {
-                int64_t n = 0;
-                for (const DevCase &d : h->dc)
-                    n += (int64_t)((d.nx + FTX - 1) / FTX) * ((d.ny + FTY - 1) / FTY) * ((d.nz + zc - 1) / zc);
-                if (n >= 512) h->zc = zc;
-            }
+        const bool f32 = o.storage == LBCG_FP32;
+        for (int zc : {32, 64, 128}) {
+            if (!f32 && zc > 64) break;
+            int64_t n = 0;
+            for (const DevCase &d : h->dc)
+                n += (int64_t)((d.nx + FTX - 1) / FTX) * ((d.ny + FTY - 1) / FTY) * ((d.nz + zc - 1) / zc);
+            if (n >= (f32 ? 512 : 2048)) h->zc = zc;
+        }
     }
     h->graph_steps = o.graph_steps + (o.graph_steps & 1);
     std::vector<int4> ftiles;
