@@ -525,7 +525,9 @@ __device__ inline Macro macro(DC &C, const NodeState &s)
 {
     Macro m;
     m.rho = s.R[0] + s.R[1];
-    m.inv_rho = 1.0f / m.rho;
+    // hardware reciprocal (1 ulp): 1/rho scales u only; rho_R/rho of the
+    // recoloring and the phase field keep correctly rounded quotients
+    m.inv_rho = __builtin_amdgcn_rcpf(m.rho);
     const float dr = m.rho - C.rho_ref;
     m.Fx = C.F[0] + dr * C.g[0];
     m.Fy = C.F[1] + dr * C.g[1];
@@ -683,7 +685,7 @@ __device__ inline void collide_node(const StepArgs &a, DC &C, int node, const No
     const float ux = M.ux, uy = M.uy, uz = M.uz, rho = M.rho;
 
     const float tv = tau_v(C, rn);
-    const float sv = 1.0f / tv, se = C.s_e, sq = C.s_q, sp = C.s_pi;
+    const float sv = __builtin_amdgcn_rcpf(tv), se = C.s_e, sq = C.s_q, sp = C.s_pi;   // 1/tau_v to 1 ulp
 
     // g_i = f_i - sum_k R_k phi_i^k, per velocity class
     const float dc0 = s.D[0] * C.phi[0][0] + s.D[1] * C.phi[1][0];
