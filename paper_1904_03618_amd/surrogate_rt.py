@@ -122,14 +122,18 @@ def train(net, trajs, box, lag, iters=400, lr=1e-3, lr_min=1e-5, seed=0, it0=0, 
     return hist
 
 
-def score(h):
-    """Model-selection key of a hybrid run on the validation case: a run that
-    ends within 1 l.u. of the LB fronts and whose jumps all stayed within
-    1 l.u. beats one that does not; then more jumps; then a smaller final
-    error."""
-    fin = h["final_front_error"]
-    ok = bool(np.isfinite(fin) and fin <= 1.0 and h["max_jump_error"] <= 1.0)
-    return (ok, h["jumps"], -float(fin) if np.isfinite(fin) else -1e9)
+def score(hs):
+    """Model-selection key of hybrid runs (one network at one number of jumps
+    per check) on the validation cases, taken at the worst of them.  Runs
+    that all keep every jump and the end within 1 l.u. of the LB fronts beat
+    any that do not; among those, the fewest jumps of any case decides (more
+    is better), then the largest final error (smaller is better).  Among the
+    others the largest final error decides, then the fewest jumps."""
+    fins = [float(h["final_front_error"]) for h in hs]
+    ok = all(np.isfinite(f) and f <= 1.0 and h["max_jump_error"] <= 1.0 for f, h in zip(fins, hs))
+    worst = -max(fins) if all(np.isfinite(f) for f in fins) else -1e9
+    jumps = min(h["jumps"] for h in hs)
+    return (1, jumps, worst) if ok else (0, worst, jumps)
 
 
 def full_domain_net(trained, box):
@@ -264,15 +268,19 @@ def hybrid(net, p, fl, every, t_start, t_end, heal=20, gate=1.0, trust=3, skill=
                 jumps_within_gate=sum(1 for e in errs if e <= gate))
 
 
-def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05, val_amp=0.045,
+def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07), eval_amp=0.05,
+               val_amps=(0.045, 0.055),
                iters=3000, segments=6, heal=20, rec=20, batch=4, slab=None, t_start=None, lr=1e-3, lr_min=1e-5,
-               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), trust=3, skill=0.5, trust_sweep=(), log=None):
+               gates=(1.0, 0.5), seeds=(7, 8, 9, 10, 11, 12), trusts=(3, 2, 1), skill=0.5, trust_sweep=(), log=None):
     """Train on LB trajectories of train_amps (whole-box inputs, pairs `every`
     steps apart from snapshots every `rec` steps) in `segments` pieces of one
     cosine schedule, once per seed (initial weights and pair sampling); after
-    each piece the gated hybrid runs on a validation amplitude (val_amp,
-    neither trained on nor evaluated) and the best weights over all seeds and
-    pieces by `score` are kept.  On the held-out amplitude eval_amp, run the
+    each piece the gated hybrid runs on validation amplitudes (val_amps,
+    neither trained on nor evaluated; by default one on each side of
+    eval_amp) with each number of jumps per passed check in `trusts`, and the
+    weights and trust that are best over all seeds, pieces and trusts by
+    `score`, the worst validation case deciding, are kept: the most jumps
+    whose drift stays within the gate on both validation cases.  On the held-out amplitude eval_amp, run the
     gated hybrid at each gate, the same gate with persistence in place of the
     network, and the plain LB run; for each value in trust_sweep, the hybrid
     at the first gate with that many jumps per passed check.  Returns a
@@ -300,8 +308,10 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
         if log:
             log(f"trajectory amp {a}: {len(tr)} snapshots, {w:.2f} s")
     stride = math.gcd(every, heal) if heal else every
-    pv, flv = case(L, val_amp)
-    ref_val = reference(pv, flv, steps, stride)
+    vcases = []
+    for a in val_amps:
+        pv, flv = case(L, a)
+        vcases.append((a, pv, flv, reference(pv, flv, steps, stride)))
     p, fl = case(L, eval_amp)
     box = (p["nx"], p["ny"], p["nz"])
     ref = reference(p, fl, steps, stride)
@@ -318,27 +328,34 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
             hs += train(net, trajs, box, every // rec, iters=n_it, lr=lr, lr_min=lr_min, seed=sd, it0=seg * per_seg,
                         total=iters, log=log)
             full.load_state(net.state_dict())
-            hv = hybrid(full, pv, flv, every, t_start, steps, heal=heal, gate=1.0, trust=trust, skill=skill,
-                        ref_fronts=ref_val)
-            key = score(hv)
-            val.append(dict(seed=sd, iters=seg * per_seg + n_it, jumps=hv["jumps"], max_jump_error=hv["max_jump_error"],
-                            final_front_error=hv["final_front_error"]))
-            if log:
-                log(f"validation seed {sd} after {val[-1]['iters']} iterations: {hv['jumps']} jumps "
-                    f"(largest error {hv['max_jump_error']:.3f}), final front error {hv['final_front_error']:.3f}")
-            if best is None or key > best[0]:
-                best = (key, net.state_dict(), len(val) - 1)
+            weights = None
+            for tr in trusts:
+                hvs = [hybrid(full, pv, flv, every, t_start, steps, heal=heal, gate=1.0, trust=tr, skill=skill,
+                              ref_fronts=rv) for _a, pv, flv, rv in vcases]
+                key = score(hvs)
+                val.append(dict(seed=sd, iters=seg * per_seg + n_it, trust=tr,
+                                cases=[dict(amp=a, jumps=hv["jumps"], max_jump_error=hv["max_jump_error"],
+                                            final_front_error=hv["final_front_error"])
+                                       for (a, *_r), hv in zip(vcases, hvs)]))
+                if log:
+                    log(f"validation seed {sd} after {val[-1]['iters']} iterations, trust {tr}: " + "; ".join(
+                        f"amp {c['amp']}: {c['jumps']} jumps (largest error {c['max_jump_error']:.3f}), final "
+                        f"front error {c['final_front_error']:.3f}" for c in val[-1]["cases"]))
+                if best is None or key > best[0]:
+                    weights = weights if weights is not None else net.state_dict()
+                    best = (key, weights, len(val) - 1)
         if not hist or hs[-1][1] < hist[-1][1]:
             hist = hs
     torch.cuda.synchronize()
     train_s = time.time() - t0
     del trajs
     full.load_state(best[1])
+    trust = val[best[2]]["trust"]
     lb = lb_time(p, fl, t_start, steps)
     res = dict(lattice=[p["nx"], p["ny"], p["nz"]], every=every, steps=steps, t_start=t_start, heal=heal,
-               train_amps=list(train_amps), val_amp=val_amp, eval_amp=eval_amp, params=net.nparams, train_iters=iters,
+               train_amps=list(train_amps), val_amps=list(val_amps), eval_amp=eval_amp, params=net.nparams, train_iters=iters,
                batch=batch, train_shape=list(net.shape), snapshot_every=rec, train_s=train_s, loss_first=hist[0][1], loss_last=min(l for _, l in hist[-5:]),
-               seeds=list(seeds), trust=trust, skill=skill, validation=val, selected_after=val[best[2]]["iters"],
+               seeds=list(seeds), trusts=list(trusts), trust=trust, skill=skill, validation=val, selected_after=val[best[2]]["iters"],
                selected_seed=val[best[2]]["seed"], lb_s=lb, trajectory_s=gen, gates={})
     for g in gates:
         hyb = hybrid(full, p, fl, every, t_start, steps, heal=heal, gate=g, trust=trust, skill=skill, ref_fronts=ref)
@@ -373,7 +390,7 @@ def experiment(L=32, every=100, steps=None, train_amps=(0.03, 0.04, 0.06, 0.07),
 def bench_summary(rt, gate=1.0):
     """The fields of an experiment() summary that the benchmark reports."""
     g = rt["gates"][str(gate)]
-    keep = ("lattice", "every", "heal", "steps", "t_start", "trust", "skill", "train_amps", "val_amp", "eval_amp",
+    keep = ("lattice", "every", "heal", "steps", "t_start", "trusts", "trust", "skill", "train_amps", "val_amps", "eval_amp",
             "train_iters", "seeds", "selected_seed", "selected_after", "train_s", "loss_first", "loss_last", "lb_s")
     out = {k: rt[k] for k in keep}
     out.update(gate_lu=gate, **{k: g[k] for k in ("hybrid_s", "gain", "jumps", "checks", "checks_passed",
@@ -396,14 +413,15 @@ def main(argv=None):
     ap.add_argument("--slab", type=int, default=0, help="train on z-slabs of this depth (0: whole box)")
     ap.add_argument("--segments", type=int, default=6)
     ap.add_argument("--seeds", default="7,8,9,10,11,12", help="training seeds; the validation picks across all of them")
-    ap.add_argument("--trust", type=int, default=3, help="jumps after each passed check")
+    ap.add_argument("--trusts", default="3,2,1", help="candidate jumps after each passed check; the validation "
+                                                      "picks one with the network")
     ap.add_argument("--skill", type=float, default=0.5, help="largest phase-field error of a passed check, "
                                                             "relative to the change over the interval")
     ap.add_argument("--trust-sweep", default="", help="further jumps-per-check values to evaluate, e.g. 1,2")
     ap.add_argument("--out", default=None, help="write the summary JSON here")
     a = ap.parse_args(argv)
     res = experiment(L=a.L, iters=a.iters, batch=a.batch, lr=a.lr, heal=a.heal, rec=a.rec, slab=a.slab or None,
-                     segments=a.segments, seeds=tuple(int(v) for v in a.seeds.split(",")), trust=a.trust,
+                     segments=a.segments, seeds=tuple(int(v) for v in a.seeds.split(",")), trusts=tuple(int(v) for v in a.trusts.split(",")),
                      skill=a.skill,
                      trust_sweep=tuple(int(v) for v in a.trust_sweep.split(",") if v), log=lambda m: print(m, flush=True))
     txt = json.dumps(res)

@@ -1,7 +1,9 @@
 """The trained surrogate on a Rayleigh-Taylor run (32 x 32 x 128): trained
 on LB snapshots of four perturbation amplitudes by the project's own MFMA
-kernels, the weights chosen by the gated hybrid on a fifth (validation)
-amplitude, evaluated on a held-out amplitude as jumps of 100 steps inside the
+kernels, the weights and the number of jumps per passed check chosen by the
+gated hybrid on two validation amplitudes (one on each side of the held-out
+one, the worse deciding: the most jumps whose drift stays within the gate),
+evaluated on a held-out amplitude as jumps of 100 steps inside the
 LB run, gated by checks inside the timed hybrid (the network's one-jump error
 on an interval the LB just computed: fronts within the gate and a phase-field
 error at most half the change over the interval).  Checks that training
