@@ -251,6 +251,8 @@ __device__ inline void pull_all(const StepArgs &a, DC &C, const Coord &c, const 
 // 16 x 16 tiles touched 4 half lines) and only 2 x 8 of the halo lies in
 // strided columns.
 constexpr int FTX = 32, FTY = 8;
+constexpr int FNT = FTX * FTY, FNW = FNT / 64;   // lanes and waves of a fused workgroup
+static_assert((FNW & (FNW - 1)) == 0, "the halo duty rotates over a power-of-two number of waves");
 constexpr int RH = 2;                    // halo of the stored-density planes around a fused tile
 constexpr int RW = FTX + 2 * RH, RREG = RW * (FTY + 2 * RH);
 
@@ -946,9 +948,9 @@ __device__ inline int ridx(int rx, int ry) { return (rx + RH) + RW * (ry + RH); 
 // being pulled) around the tile into the LDS plane ring: the tile plus RH
 // nodes on each side, which covers every pull source of the tile's nodes and
 // of its halo.  Planes beyond a wall are not copied (their pulls bounce back).
-// Split into the loads (two rounds of at most RREG = 484 entries, issued
-// together and early) and the LDS stores, so that their latency hides behind
-// the pulls issued in between.
+// Split into the loads (RREG entries in two rounds over the workgroup's
+// lanes, issued together and early) and the LDS stores, so that their
+// latency hides behind the pulls issued in between.
 // IN = LV_COMPACT: the writers' recoloring data are staged the same way into
 // rings of their own.
 template <int IN> struct RhoStage {
@@ -970,12 +972,12 @@ __device__ inline RhoStage<IN> fused_stage_load(const StepArgs &a, DC &C, int zl
     } else {
         zp = (zl + 4 * C.nz) % C.nz;
     }
-    static_assert(RREG <= 512, "the writers' region must fit two rounds of 256 lanes");
+    static_assert(RREG <= 2 * FNT, "the writers' region must fit two rounds of the workgroup's lanes");
     const size_t pofs = (size_t)C.node_off + (size_t)C.nx * C.ny * zp;
     const int w = ax + 2 * RH, n = w * (ay + 2 * RH);
     #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        const int e0 = (int)threadIdx.x + 256 * k;
+        const int e0 = (int)threadIdx.x + FNT * k;
         const int e = min(e0, n - 1);                   // lanes past the region reload its last entry
         const int ry = e / w, rx = e - ry * w;
         // periodic wrap without branches (the region reaches RH < 4 nodes beyond the box)
@@ -1069,7 +1071,7 @@ __device__ inline void fused_ring2(const StepArgs &a, DC &C, float4 *slot, float
                                    int zp, int x0, int y0, int ax, int ay)
 {
     const int n = 2 * (ax + 4) + 2 * (ay + 2);
-    for (int e = (int)threadIdx.x; e < n; e += 256) {
+    for (int e = (int)threadIdx.x; e < n; e += FNT) {
         int rx, ry;
         ring2_pos(e, ax, ay, rx, ry);
         const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
@@ -1087,12 +1089,12 @@ __device__ inline void fused_ring2(const StepArgs &a, DC &C, float4 *slot, float
 // Aux values of plane zp (0 <= zp < nz) into the ring slot of plane zl (zl =
 // zp, or zp -+ nz for the periodic neighbours of the chunk's end planes): the
 // lane's own node (pulled state kept in s) and the halo of width h (1, or 2
-// on a wall layer).  The halo holds at most 144 nodes, so a lane pulls at
-// most one halo node; the halo duty falls on consecutive waves, rotated by
-// plane.  Lanes outside a ragged tile (and past the halo)
-// pull a valid node and drop the result.  On a wall layer of a case with
-// moving walls the density factor qs of Qbar goes to wq[side] for the ghost
-// layer.
+// on a wall layer).  The one-node halo (84 nodes around a 32 x 8 tile) is
+// smaller than the workgroup, so a lane pulls at most one halo node; the
+// halo duty falls on consecutive waves, rotated by plane.  Lanes outside a
+// ragged tile (and past the halo) pull a valid node and drop the result.  On
+// a wall layer of a case with moving walls the density factor qs of Qbar goes
+// to wq[side] for the ghost layer.
 template <int ST, bool MV, int WL, int IN>
 __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], float2 (*rring)[RREG],
                                    const float4 *dring, const float *cring, float (*wq)[FREG], int zl, int zp,
@@ -1112,10 +1114,10 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
     }
     // the one-node ring here; a wall layer's second ring after it (fused_ring2)
     const int w = ax + 2, nrow = 2 * w, nh = nrow + 2 * ay;
-    const int rot = zl & 3;
-    const int e = ((int)threadIdx.x - 64 * rot + 256) & 255;
+    const int rot = zl & (FNW - 1);
+    const int e = ((int)threadIdx.x - 64 * rot + FNT) & (FNT - 1);
     const int wave = (int)threadIdx.x >> 6;
-    const bool wave_halo = __builtin_amdgcn_readfirstlane((((wave - rot) & 3) * 64 < nh) ? 1 : 0) != 0;
+    const bool wave_halo = __builtin_amdgcn_readfirstlane((((wave - rot) & (FNW - 1)) * 64 < nh) ? 1 : 0) != 0;
     if constexpr (sizeof(P) == 8 && IN == LV_PAIR) {
         // FP32 pairs: a wave with halo duty issues both nodes' loads before it
         // waits (one memory latency instead of two, at 2 waves per SIMD)
@@ -1170,7 +1172,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             if (wlo) wq[0][fidx(tx, ty)] = qs;
             if (whi) wq[1][fidx(tx, ty)] = qs;
         }
-        for (int eh = e; eh < nh; eh += 256) {
+        for (int eh = e; eh < nh; eh += FNT) {
             int rx, ry;
             halo_pos(eh, w, nrow, 1, ax, ay, rx, ry);
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
@@ -1198,7 +1200,7 @@ __device__ inline void fused_ghost(DC &C, float4 (*ring)[FREG], float (*wq)[FREG
     const float4 *src = ring[fslot(side ? C.nz - 1 : 0)];
     float4 *dst = ring[fslot(side ? C.nz : -1)];
     const int w = ax + 2, n = w * (ay + 2);
-    for (int e = (int)threadIdx.x; e < n; e += 256) {
+    for (int e = (int)threadIdx.x; e < n; e += FNT) {
         const int ry = e / w - 1, rx = e - (ry + 1) * w - 1;
         float gb = 0.f, gc = 0.f;
         #pragma unroll
@@ -1238,7 +1240,7 @@ __device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int tx, int ty, 
 // IN, OUT: level format read and written (LV_PAIR -> LV_PAIR, or -> LV_COMPACT;
 // LV_COMPACT -> LV_COMPACT).
 template <int ST, bool MV, int WL, int IN, int OUT>
-__global__ __launch_bounds__(256) void k_fused(FusedArgs fa)
+__global__ __launch_bounds__(FNT) void k_fused(FusedArgs fa)
 {
     __shared__ float4 ring[FSLOTS][FREG];
     __shared__ float2 rring[4][RREG];

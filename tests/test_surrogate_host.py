@@ -28,3 +28,30 @@ def test_flop_count_by_hand():
     # training: forward + weight gradients of every layer + data gradients of all but the first
     assert got_train == 3 * fwd - first
     assert abs(fwd / 1e9 - 1110.0) < 0.1
+
+
+def test_selection_key_prefers_bounded_drift_then_jumps():
+    """The validation key of the surrogate pipeline, on hand-made run
+    summaries: a candidate counts as within the gate only if every validation
+    case keeps its largest jump and its end within 1 l.u.; among those the
+    fewest jumps of any case decide (so a trust that is safe on both cases but
+    takes fewer jumps loses to one that is safe and takes more), and among the
+    rest the worst final error decides before the jumps."""
+    from paper_1904_03618_amd import surrogate_rt as R
+
+    def run(jumps, largest, final):
+        return dict(jumps=jumps, max_jump_error=largest, final_front_error=final)
+
+    safe23 = [run(23, 0.51, 0.41), run(23, 0.43, 0.37)]
+    safe31 = [run(31, 0.90, 0.95), run(32, 0.99, 0.97)]
+    one_side = [run(32, 0.91, 0.92), run(33, 3.22, 3.23)]     # fine on one amplitude only
+    drift_small = [run(31, 1.35, 1.33), run(31, 1.73, 1.75)]
+    drift_large = [run(33, 4.96, 5.04), run(33, 3.40, 3.45)]
+    nan_end = [run(33, 0.5, float("nan")), run(33, 0.5, 0.5)]
+    keys = {name: R.score(v) for name, v in dict(safe23=safe23, safe31=safe31, one_side=one_side,
+                                                 drift_small=drift_small, drift_large=drift_large,
+                                                 nan_end=nan_end).items()}
+    order = sorted(keys, key=keys.get, reverse=True)
+    assert order == ["safe31", "safe23", "drift_small", "one_side", "drift_large", "nan_end"]
+    # the unsafe candidates all rank below every safe one
+    assert all(keys[s] > keys[u] for s in ("safe23", "safe31") for u in ("one_side", "drift_small", "nan_end"))
