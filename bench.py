@@ -84,7 +84,7 @@ def timed_run(B, cases, storage, steps, warmup, kernel_steps=100, repeats=0, rep
     import torch
     s = B.Solver(cases, storage=storage, **opts)
     if layout is not None:
-        layout.update(kernel=B.lbcg_step_kernel(s.h), level=B.lbcg_level_format(s.h))
+        layout.update(kernel=B.lbcg_step_kernel(s.h), level=B.lbcg_level_format(s.h), zchunk=B.lbcg_zchunk(s.h))
     try:
         stream = torch.cuda.current_stream()
         s.step(warmup)
@@ -301,7 +301,8 @@ def main():
         err_u = float(max((ff[k] - ref[k]).abs().max() for k in ("ux", "uy", "uz")))
         froof = roofline(fkt, st, N, fms, flay["level"])
         froof["traffic"] = measured_traffic(froof["kernel"].split("<")[0], st, "rt128x128x512")
-        forms[st] = {"MLUPS": N / (fms * 1e-3) / 1e6, "ms_per_step": fms, "kernels_avg_ms": fkt,
+        forms[st] = {"MLUPS": N / (fms * 1e-3) / 1e6, "ms_per_step": fms, "zchunk": flay["zchunk"],
+                     "kernels_avg_ms": fkt,
                      "roofline": froof, "vs_fp32": N / (fms * 1e-3) / 1e6 / mlups,
                      "max_abs_diff_vs_fp32_after_steps": {"rhoN": err_n, "u": err_u,
                                                           "steps": args.steps + args.warmup}}
@@ -315,7 +316,8 @@ def main():
             llay = {}
             lms, lkt, _, _ = timed_run(B, [(pl, fll)], st, min(args.steps, 100), 5, kernel_steps=20, layout=llay,
                                        kernel=args.kernel)
-            big[st] = {"MLUPS": NL / (lms * 1e-3) / 1e6, "ms_per_step": lms, "kernels_avg_ms": lkt,
+            big[st] = {"MLUPS": NL / (lms * 1e-3) / 1e6, "ms_per_step": lms, "zchunk": llay["zchunk"],
+                       "kernels_avg_ms": lkt,
                        "roofline": roofline(lkt, st, NL, lms, llay["level"])}
         del fll
         extra["rayleigh_taylor_256x256x1024"] = big
@@ -326,7 +328,8 @@ def main():
         for st in ("fp32", "fp16s"):
             glay = {}
             gms, gkt, _, _ = timed_run(B, [(pg, flg)], st, args.steps, args.warmup, layout=glay, kernel=args.kernel)
-            gal[st] = {"MLUPS": NG / (gms * 1e-3) / 1e6, "ms_per_step": gms, "kernels_avg_ms": gkt,
+            gal[st] = {"MLUPS": NG / (gms * 1e-3) / 1e6, "ms_per_step": gms, "zchunk": glay["zchunk"],
+                       "kernels_avg_ms": gkt,
                        "roofline": roofline(gkt, st, NG, gms, glay["level"])}
         extra["galilean_droplet_128"] = gal
 
@@ -340,7 +343,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "rayleigh-taylor 128x128x512 (walls on z, At 0.5, g 2e-5, Re 1024, amplitude 0.05 L)",
                    "lattice": [128, 128, 512], "storage": "fp32", "kernel": lay["kernel"],
-                   "level_format": lay["level"],
+                   "level_format": lay["level"], "zchunk": lay["zchunk"],
                    "tau_v": list(p["tau_v"]), "parallelism": "single GPU"},
         "repeat_runs": {"runs": len(reps), "steps": 200, "ms_per_step": reps,
                         "median_MLUPS": N / (float(np.median(reps)) * 1e-3) / 1e6 if reps else None},

@@ -133,9 +133,13 @@ typedef struct lbcg_fields {
  * the two-pass kernels (0 = default 256; 64, 128, 192 or 256).
  * persistent_blocks: 0 = one workgroup per tile, >0 = that many workgroups
  * looping over all tiles of all cases (batched persistent launch).
- * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default: the
- * longest of 16, 32, 64, 128 that leaves at least 512 tiles for FP32, of 16,
- * 32, 64 that leaves at least 2048 tiles for the 16-bit forms, else 16).
+ * kernel: LBCG_KERNEL_*.  zchunk: z-planes per fused tile (0 = default: with
+ * T(zc) tiles of all cases and S workgroup slots for the fused kernel the
+ * handle runs (CUs x the workgroups per CU that its registers and LDS allow,
+ * queried from the runtime at init; a failed query is LBCG_EDEVICE), the
+ * chunk in 8 .. 128 planes (FP32) or 8 .. 64 (16-bit forms) that minimises
+ * ceil(T / S) (zc + 2), the longer on a tie, or the longest where that one
+ * gives T >= 2 S; lbcg_zchunk reports it).
  * graph_steps: 0 = launch every kernel of every step; n > 0 = capture n steps
  * (rounded up to even) once into a HIP graph and replay it; with diag_every
  * the stability check then runs at the first replay boundary at or after each
@@ -240,13 +244,15 @@ int lbcg_timing(lbcg_handle *h, int32_t enable);
 int lbcg_timing_read(lbcg_handle *h, double *ms, int64_t *launches);
 
 /* Number of nodes and storage bytes per population value of the handle;
- * the handle's step kernel (LBCG_KERNEL_TWOPASS or LBCG_KERNEL_FUSED) and
- * level format (LBCG_LEVEL_PAIR or LBCG_LEVEL_COMPACT) as resolved at init.
- * -1 for an invalid handle or case. */
+ * the handle's step kernel (LBCG_KERNEL_TWOPASS or LBCG_KERNEL_FUSED), level
+ * format (LBCG_LEVEL_PAIR or LBCG_LEVEL_COMPACT) and fused z-chunk in planes
+ * (0 with the two-pass step) as resolved at init.  -1 for an invalid handle
+ * or case. */
 int64_t lbcg_case_nodes(const lbcg_handle *h, int32_t case_id);
 int32_t lbcg_storage_bytes(const lbcg_handle *h);
 int32_t lbcg_step_kernel(const lbcg_handle *h);
 int32_t lbcg_level_format(const lbcg_handle *h);
+int32_t lbcg_zchunk(const lbcg_handle *h);
 
 /* Checkpoint / resume.  The state of a handle at its current level is the
  * stored population values of every case (raw bits, storage format of the

@@ -24,7 +24,8 @@ STORAGE = {"fp32": LBCG_FP32, "fp16s": LBCG_FP16S, "bf16s": LBCG_BF16S}
 EXPORTS = ("lbcg_init", "lbcg_step", "lbcg_moments", "lbcg_free", "lbcg_last_error",
            "lbcg_steps_done", "lbcg_index_map", "lbcg_get_populations", "lbcg_case_nodes",
            "lbcg_storage_bytes", "lbcg_timing", "lbcg_timing_read", "lbcg_set_fields", "lbcg_checkpoint_bytes",
-           "lbcg_checkpoint_save", "lbcg_checkpoint_load", "lbcg_step_kernel", "lbcg_level_format")
+           "lbcg_checkpoint_save", "lbcg_checkpoint_load", "lbcg_step_kernel", "lbcg_level_format",
+           "lbcg_zchunk")
 
 
 class LbcgError(RuntimeError):
@@ -96,7 +97,7 @@ def load():
     L.lbcg_case_nodes.restype = i64
     L.lbcg_storage_bytes.argtypes = [vp]
     L.lbcg_storage_bytes.restype = i32
-    for name in ("lbcg_step_kernel", "lbcg_level_format"):
+    for name in ("lbcg_step_kernel", "lbcg_level_format", "lbcg_zchunk"):
         getattr(L, name).argtypes = [vp]
         getattr(L, name).restype = i32
     L.lbcg_timing.argtypes = [vp, i32]
@@ -215,6 +216,11 @@ def lbcg_step_kernel(h):
 def lbcg_level_format(h):
     """'pair' or 'compact': the level format the handle resolved at init."""
     return {LBCG_LEVEL_PAIR: "pair", LBCG_LEVEL_COMPACT: "compact"}[int(load().lbcg_level_format(C.c_void_p(h)))]
+
+
+def lbcg_zchunk(h):
+    """z-planes per fused tile the handle resolved at init (0: two-pass step)."""
+    return int(load().lbcg_zchunk(C.c_void_p(h)))
 
 
 def lbcg_set_fields(h, case_id, rhoR, rhoB, ux, uy, uz):

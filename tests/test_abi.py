@@ -182,3 +182,4 @@ def test_never_issued_handle_is_rejected_without_being_read():
     assert L.lbcg_steps_done(bogus) == -1 and L.lbcg_case_nodes(bogus, 0) == -1
     assert L.lbcg_storage_bytes(bogus) == -1 and L.lbcg_checkpoint_bytes(bogus) == -1
     assert L.lbcg_step_kernel(bogus) == -1 and L.lbcg_level_format(bogus) == -1
+    assert L.lbcg_zchunk(bogus) == -1

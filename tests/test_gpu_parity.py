@@ -351,6 +351,41 @@ def test_auto_resolves_kernel_and_level():
             B.lbcg_free(h)
 
 
+def test_default_chunk_fills_the_workgroup_slots():
+    """The default z-chunk minimises ceil(T / S) (zc + 2) over 8 .. 128 planes
+    (FP32) or 8 .. 64 (16-bit forms), the longer on a tie, with T(zc) the
+    tiles of 32 x 8 columns and S the GPU's workgroup slots: CUs x workgroups
+    per CU of the kernel, as built 2 for FP32 compact levels (229 VGPRs, 76 KB
+    LDS) and 3 for 16-bit pairs (167 VGPRs, 41 KB).  Boxes chosen so that
+    neither bound decides (e.g. 128 x 64 x 256: 17 planes would still fill
+    the slots but leave a last chunk of one plane; 16 balances)."""
+    import torch
+    from paper_1904_03618_amd import lbcg as B
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+
+    def rule(nx, ny, nz, slots, cap):
+        cols = -(-nx // 32) * -(-ny // 8)
+        if cols * -(-nz // cap) >= 2 * slots:
+            return cap
+        best = None
+        for zc in range(cap, 7, -1):
+            cost = -(-cols * -(-nz // zc) // slots) * (zc + 2)
+            if best is None or cost < best[0]:
+                best = (cost, zc)
+        return best[1]
+
+    for nx, ny, nz in ((128, 64, 256), (128, 128, 160)):
+        case = W.random_state_case(nx, ny, nz, seed=7, bc=(0, 0, 1))
+        for storage, per_cu, cap in (("fp32", 2, 128), ("fp16s", 3, 64)):
+            h = B.lbcg_init([case], storage=storage)
+            try:
+                want = rule(nx, ny, nz, cus * per_cu, cap)
+                assert 8 < want < cap
+                assert B.lbcg_zchunk(h) == want, (nx, ny, nz, storage, B.lbcg_zchunk(h), want)
+            finally:
+                B.lbcg_free(h)
+
+
 def test_compact_handle_with_a_reinitialised_case():
     """In a compact handle, lbcg_set_fields puts one case back to a pair-format
     start level while the other stays compact: the next step runs the two
