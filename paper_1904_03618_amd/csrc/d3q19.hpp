@@ -67,14 +67,17 @@ template <> struct Storage<LBCG_FP32> {
 template <> struct Storage<LBCG_FP16S> {
     using T = _Float16;
     using P = Pair<T>;
-    __device__ static float dec(T v, float inv_scale) { return (float)v * inv_scale; }
+    // the scale is a power of two, so the product is exact and one
+    // mixed-precision FMA (conversion and multiply fused) gives the same value
+    __device__ static float dec(T v, float inv_scale) { return __builtin_fmaf((float)v, inv_scale, 0.0f); }
     __device__ static T enc(float d, float scale) { return (T)(d * scale); }
 };
 template <> struct Storage<LBCG_BF16S> {
     using T = __bf16;
     using P = Pair<T>;
-    __device__ static float dec(T v, float inv_scale) { return (float)v * inv_scale; }
-    __device__ static T enc(float d, float scale) { return (T)(d * scale); }
+    // BF16's exponent range needs no scale (the handle's scale is 1)
+    __device__ static float dec(T v, float) { return (float)v; }
+    __device__ static T enc(float d, float) { return (T)d; }
 };
 
 // Cache policy of the population streams: loads are non-temporal, so that a
