@@ -28,6 +28,7 @@ def test_surrogate_gated_hybrid_on_rayleigh_taylor():
     print(json.dumps(res), flush=True)
     g = res["gates"]["1.0"]
     assert res["loss_last"] < 0.5 * res["loss_first"]
+    assert res["validated"]
     assert g["jumps"] > 0 and g["checks_passed"] > 0
     assert g["persistence"]["checks_passed"] == 0 and g["persistence"]["jumps"] == 0
     assert g["jumps"] > g["persistence"]["jumps"]
