@@ -7,7 +7,9 @@ evaluated on a held-out amplitude as jumps of 100 steps inside the
 LB run, gated by checks inside the timed hybrid (the network's one-jump error
 on an interval the LB just computed: fronts within the gate and a phase-field
 error at most half the change over the interval).  Checks that training
-lowers the loss, that the network passes checks and jumps where persistence
+lowers the loss, that some candidate validated (kept its drift within the gate
+on both validation amplitudes), that the network passes checks and jumps
+where persistence
 (the same gate with the state left unchanged) never passes, that most jumps
 land within the gate of the plain LB run's fronts and the run ends within 1.5
 gates of them; prints the time-to-solution gain over plain LB, checks
@@ -32,9 +34,9 @@ def test_surrogate_gated_hybrid_on_rayleigh_taylor():
     assert g["jumps"] > 0 and g["checks_passed"] > 0
     assert g["persistence"]["checks_passed"] == 0 and g["persistence"]["jumps"] == 0
     assert g["jumps"] > g["persistence"]["jumps"]
-    # the check bounds one jump's error; over ~30 jumps the errors accumulate
-    # (about 0.03 l.u. per jump), so the run's end is held to 1.5 gates and
-    # most single jumps to the gate
+    # the check bounds one jump's error; over 20-30 jumps the errors
+    # accumulate (0.01-0.03 l.u. per jump), so the run's end is held to 1.5
+    # gates and most single jumps to the gate
     assert g["final_front_error"] <= 1.5
     assert g["jumps_within_gate"] >= 0.8 * g["jumps"]
 
