@@ -119,6 +119,25 @@ __device__ inline T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
     }
 }
 
+// The same with a wave-uniform byte offset soff added by the hardware (a
+// scalar operand, no per-lane address arithmetic).
+template <class T, int CP>
+__device__ inline T buf_ld_so(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, uint32_t soff)
+{
+    if constexpr (sizeof(T) == 2) {
+        const unsigned short v = __builtin_amdgcn_raw_buffer_load_b16(r, (int)byte_off, (int)soff, CP);
+        return __builtin_bit_cast(T, v);
+    } else if constexpr (sizeof(T) == 4) {
+        const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, (int)soff, CP);
+        return __builtin_bit_cast(T, v);
+    } else {
+        static_assert(sizeof(T) == 8, "buffer element size");
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, (int)soff, CP);
+        return __builtin_bit_cast(T, v);
+    }
+}
+
 template <class T, int CP>
 __device__ inline void buf_st(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, T val)
 {

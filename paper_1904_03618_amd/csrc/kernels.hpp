@@ -393,7 +393,11 @@ template <int ST> struct CompactPull {
     typename Storage<ST>::T v[Q];
 };
 
-template <int ST, int CPP, int I = 1>
+// SO: the case's whole level lies within one buffer resource (20 NS values
+// below 2^31 bytes), and each direction pair's array is reached by a scalar
+// offset; otherwise each pair has a resource of its own (any size, but the
+// ten resources stay live in scalar registers across the plane loop).
+template <int ST, int CPP, bool SO = false, int I = 1>
 __device__ inline void pull_issue_c(const StepArgs &a, DC &C, const Coord &c, CompactPull<ST> &p)
 {
     using S = Storage<ST>;
@@ -401,8 +405,12 @@ __device__ inline void pull_issue_c(const StepArgs &a, DC &C, const Coord &c, Co
     using P = typename S::P;
     const size_t NS = (size_t)C.NS;
     const T *base0 = reinterpret_cast<const T *>(a.fin) + C.pop_off;
-    if constexpr (I == 1)
-        p.v0 = buf_ld<P, CPP>(rsrc(base0, NS * sizeof(P)), (uint32_t)c.node * (uint32_t)sizeof(P));
+    if constexpr (I == 1) {
+        if constexpr (SO)
+            p.v0 = buf_ld_so<P, CPP>(rsrc(base0, 20 * NS * sizeof(T)), (uint32_t)c.node * (uint32_t)sizeof(P), 0u);
+        else
+            p.v0 = buf_ld<P, CPP>(rsrc(base0, NS * sizeof(P)), (uint32_t)c.node * (uint32_t)sizeof(P));
+    }
     if constexpr (I < Q) {
         constexpr int F = pair_first<I>();
         const bool bb = bounce<I>(c);
@@ -410,8 +418,12 @@ __device__ inline void pull_issue_c(const StepArgs &a, DC &C, const Coord &c, Co
         constexpr bool hi_own = I != F, hi_opp = opp(I) != F;
         const bool hi = bb ? hi_opp : hi_own;
         const uint32_t e = si + (hi ? (uint32_t)NS : 0u);
-        p.v[I] = buf_ld<T, CPP>(rsrc(base0 + (size_t)(F + 1) * NS, 2 * NS * sizeof(T)), e * (uint32_t)sizeof(T));
-        pull_issue_c<ST, CPP, I + 1>(a, C, c, p);
+        if constexpr (SO)
+            p.v[I] = buf_ld_so<T, CPP>(rsrc(base0, 20 * NS * sizeof(T)), e * (uint32_t)sizeof(T),
+                                       (uint32_t)((F + 1) * NS * sizeof(T)));
+        else
+            p.v[I] = buf_ld<T, CPP>(rsrc(base0 + (size_t)(F + 1) * NS, 2 * NS * sizeof(T)), e * (uint32_t)sizeof(T));
+        pull_issue_c<ST, CPP, SO, I + 1>(a, C, c, p);
     }
 }
 
@@ -1014,10 +1026,10 @@ template <int ST, int IN> struct FPull;
 template <int ST> struct FPull<ST, LV_PAIR> { typename Storage<ST>::P v[Q]; };
 template <int ST> struct FPull<ST, LV_COMPACT> : CompactPull<ST> {};
 
-template <int ST, int IN, int CPP>
+template <int ST, int IN, int CPP, bool SO = false>
 __device__ inline void fpull_issue(const StepArgs &a, DC &C, const Coord &c, FPull<ST, IN> &p)
 {
-    if constexpr (IN == LV_COMPACT) pull_issue_c<ST, CPP>(a, C, c, p);
+    if constexpr (IN == LV_COMPACT) pull_issue_c<ST, CPP, SO>(a, C, c, p);
     else pull_issue<ST, CPP>(a, C, c, p.v);
 }
 
@@ -1095,7 +1107,7 @@ __device__ inline void fused_ring2(const StepArgs &a, DC &C, float4 *slot, float
 // ragged tile (and past the halo) pull a valid node and drop the result.  On
 // a wall layer of a case with moving walls the density factor qs of Qbar goes
 // to wq[side] for the ghost layer.
-template <int ST, bool MV, int WL, int IN>
+template <int ST, bool MV, int WL, int IN, bool SO = false>
 __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG], float2 (*rring)[RREG],
                                    const float4 *dring, const float *cring, float (*wq)[FREG], int zl, int zp,
                                    int x0, int y0, int ax, int ay, int h, bool active, int tx, int ty,
@@ -1124,7 +1136,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         const int ox = min(tx, ax - 1), oy = min(ty, ay - 1);
         const Coord co = make_coord_xyz<WL>(C, x0 + ox, y0 + oy, zp);
         FPull<ST, IN> vo;
-        fpull_issue<ST, IN, CP_DEFAULT>(a, C, co, vo);
+        fpull_issue<ST, IN, CP_DEFAULT, SO>(a, C, co, vo);
         float qs;
         if (wave_halo) {
             const int eh = min(e, nh - 1);
@@ -1133,7 +1145,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
             const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
             FPull<ST, IN> vh;
-            fpull_issue<ST, IN, CP_DEFAULT>(a, C, ch, vh);
+            fpull_issue<ST, IN, CP_DEFAULT, SO>(a, C, ch, vh);
             __builtin_amdgcn_sched_barrier(0);   // both nodes' loads issued before the first use
             fpull_finish<ST, IN, MV>(a, C, co, wr, ridx(ox, oy), vo, s);
             if (active) {
@@ -1165,7 +1177,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
         if (active) {
             const Coord co = make_coord_xyz<WL>(C, x0 + tx, y0 + ty, zp);
             FPull<ST, IN> vo;
-            fpull_issue<ST, IN, CP_DEFAULT>(a, C, co, vo);
+            fpull_issue<ST, IN, CP_DEFAULT, SO>(a, C, co, vo);
             __builtin_amdgcn_sched_barrier(0);
             fpull_finish<ST, IN, MV>(a, C, co, wr, ridx(tx, ty), vo, s);
             slot[fidx(tx, ty)] = aux_value(C, s, qs);
@@ -1178,7 +1190,7 @@ __device__ inline void fused_plane(const StepArgs &a, DC &C, float4 (*ring)[FREG
             const int gx = (x0 + rx + 4 * C.nx) % C.nx, gy = (y0 + ry + 4 * C.ny) % C.ny;
             const Coord ch = make_coord_xyz<WL>(C, gx, gy, zp);
             FPull<ST, IN> vh;
-            fpull_issue<ST, IN, CP_DEFAULT>(a, C, ch, vh);
+            fpull_issue<ST, IN, CP_DEFAULT, SO>(a, C, ch, vh);
             __builtin_amdgcn_sched_barrier(0);
             NodeState hs;
             fpull_finish<ST, IN, MV>(a, C, ch, wr, ridx(rx, ry), vh, hs);
@@ -1239,7 +1251,9 @@ __device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int tx, int ty, 
 // WL: WALLS_NONE or WALLS_Z (cases with walls on other axes take the two-pass step).
 // IN, OUT: level format read and written (LV_PAIR -> LV_PAIR, or -> LV_COMPACT;
 // LV_COMPACT -> LV_COMPACT).
-template <int ST, bool MV, int WL, int IN, int OUT>
+// SO: compact levels read through one buffer resource per case (the host
+// takes it where every case's level is below 2^31 bytes).
+template <int ST, bool MV, int WL, int IN, int OUT, bool SO = false>
 __global__ __launch_bounds__(FNT) void k_fused(FusedArgs fa)
 {
     __shared__ float4 ring[FSLOTS][FREG];
@@ -1266,11 +1280,11 @@ __global__ __launch_bounds__(FNT) void k_fused(FusedArgs fa)
         NodeState cur, nxt;
         // plane z0 (kept) and the plane below it (the top plane, for a
         // periodic z at z0 = 0); at a bottom wall the ghost layer instead
-        fused_plane<ST, MV, WL, IN>(a, C, ring, rring, dring, cring, wq, z0, z0, x0, y0, ax, ay,
-                                walls && (z0 == 0 || z0 == C.nz - 1) ? 2 : 1, active, tx, ty, cur);
+        fused_plane<ST, MV, WL, IN, SO>(a, C, ring, rring, dring, cring, wq, z0, z0, x0, y0, ax, ay,
+                                        walls && (z0 == 0 || z0 == C.nz - 1) ? 2 : 1, active, tx, ty, cur);
         if (!(walls && z0 == 0))
-            fused_plane<ST, MV, WL, IN>(a, C, ring, rring, dring, cring, wq, z0 - 1, z0 == 0 ? C.nz - 1 : z0 - 1,
-                                        x0, y0, ax, ay, 1, active, tx, ty, nxt);
+            fused_plane<ST, MV, WL, IN, SO>(a, C, ring, rring, dring, cring, wq, z0 - 1,
+                                            z0 == 0 ? C.nz - 1 : z0 - 1, x0, y0, ax, ay, 1, active, tx, ty, nxt);
         __syncthreads();
         fused_stage_store<IN>(rring, dring, cring, z0 + 2,
                               fused_stage_load<IN>(a, C, z0 + 2, x0, y0, ax, ay, walls));
@@ -1287,8 +1301,8 @@ __global__ __launch_bounds__(FNT) void k_fused(FusedArgs fa)
                 fused_ghost<MV>(C, ring, wq, 1, ax, ay);
             } else {
                 const int zp = zn == C.nz ? 0 : zn;        // periodic wrap
-                fused_plane<ST, MV, WL, IN>(a, C, ring, rring, dring, cring, wq, zn, zp, x0, y0, ax, ay,
-                                            walls && zp == C.nz - 1 ? 2 : 1, active, tx, ty, nxt);
+                fused_plane<ST, MV, WL, IN, SO>(a, C, ring, rring, dring, cring, wq, zn, zp, x0, y0, ax, ay,
+                                                walls && zp == C.nz - 1 ? 2 : 1, active, tx, ty, nxt);
             }
             fused_stage_store<IN>(rring, dring, cring, z + 3, rs);
             __syncthreads();

@@ -59,6 +59,7 @@ struct lbcg_handle {
     float4 *dsc[2] = {nullptr, nullptr};
     float *crs[2] = {nullptr, nullptr};
     std::vector<uint8_t> pairlvl;      // per case: its current level is in pair format
+    bool one_rsrc = false;             // every case's compact level fits one buffer resource (< 2^31 bytes)
     double *partial = nullptr, *red = nullptr;
     int64_t steps = 0, total_nodes = 0, total_pop = 0, total_ghost = 0;
     float scale = 1.0f, inv_scale = 1.0f;
@@ -264,27 +265,51 @@ int for_format_runs(const lbcg_handle *h, F &&f)
     return LBCG_OK;
 }
 
-template <int ST, int IN, int OUT>
+template <int ST, int IN, int OUT, bool SO>
 void launch_fused(lbcg_handle *h, hipStream_t st, const FusedArgs &fa, int grid)
 {
     const dim3 g(grid), b(FTX * FTY);
-    if (h->moving) hipLaunchKernelGGL((k_fused<ST, true, WALLS_Z, IN, OUT>), g, b, 0, st, fa);
-    else if (h->walls == WALLS_Z) hipLaunchKernelGGL((k_fused<ST, false, WALLS_Z, IN, OUT>), g, b, 0, st, fa);
-    else hipLaunchKernelGGL((k_fused<ST, false, WALLS_NONE, IN, OUT>), g, b, 0, st, fa);
+    if (h->moving) hipLaunchKernelGGL((k_fused<ST, true, WALLS_Z, IN, OUT, SO>), g, b, 0, st, fa);
+    else if (h->walls == WALLS_Z) hipLaunchKernelGGL((k_fused<ST, false, WALLS_Z, IN, OUT, SO>), g, b, 0, st, fa);
+    else hipLaunchKernelGGL((k_fused<ST, false, WALLS_NONE, IN, OUT, SO>), g, b, 0, st, fa);
+}
+
+// Compact input levels of a handle whose cases all fit one buffer resource
+// take the single-resource instantiation (fewer scalar registers live).
+template <int ST, int IN, int OUT>
+void launch_fused(lbcg_handle *h, hipStream_t st, const FusedArgs &fa, int grid)
+{
+    if constexpr (IN == LV_COMPACT) {
+        if (h->one_rsrc) {
+            launch_fused<ST, IN, OUT, true>(h, st, fa, grid);
+            return;
+        }
+    }
+    launch_fused<ST, IN, OUT, false>(h, st, fa, grid);
 }
 
 // Workgroups of the handle's steady-state fused kernel that one CU holds at
 // once (its registers and LDS), as the runtime computes it; 0 on failure.
-template <int ST, int LV>
+template <int ST, int LV, bool SO>
 int fused_blocks_per_cu(const lbcg_handle *h)
 {
     int nb = 0;
     hipError_t e;
-    if (h->moving) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<ST, true, WALLS_Z, LV, LV>, FNT, 0);
+    if (h->moving)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<ST, true, WALLS_Z, LV, LV, SO>, FNT, 0);
     else if (h->walls == WALLS_Z)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<ST, false, WALLS_Z, LV, LV>, FNT, 0);
-    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<ST, false, WALLS_NONE, LV, LV>, FNT, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<ST, false, WALLS_Z, LV, LV, SO>, FNT, 0);
+    else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_fused<ST, false, WALLS_NONE, LV, LV, SO>, FNT, 0);
     return e == hipSuccess ? nb : 0;
+}
+
+template <int ST, int LV>
+int fused_blocks_per_cu(const lbcg_handle *h)
+{
+    if constexpr (LV == LV_COMPACT) {
+        if (h->one_rsrc) return fused_blocks_per_cu<ST, LV, true>(h);
+    }
+    return fused_blocks_per_cu<ST, LV, false>(h);
 }
 
 int fused_blocks_per_cu(const lbcg_handle *h)
@@ -657,6 +682,9 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
                    ? LV_COMPACT
                    : LV_PAIR;
     h->pairlvl.assign(n_cases, 1);
+    h->one_rsrc = true;
+    for (const DevCase &d : h->dc)
+        if ((int64_t)20 * d.NS * (o.storage == LBCG_FP32 ? 4 : 2) >= ((int64_t)1 << 31)) h->one_rsrc = false;
     h->zc = o.zchunk;
     if (h->zc == 0 && h->fused) {
         // default chunk: a workgroup's tile of zc planes pulls zc + 2 planes,

@@ -386,6 +386,24 @@ def test_default_chunk_fills_the_workgroup_slots():
                 B.lbcg_free(h)
 
 
+def test_compact_levels_beyond_one_buffer_resource():
+    """A case whose compact FP32 level reaches 2^31 bytes (a 256 x 256 x 416
+    Rayleigh-Taylor box, 27.3 M nodes) reads it through one buffer resource
+    per direction pair (smaller levels take one resource per level and
+    scalar offsets): after 20 steps it agrees with the same case on pair
+    levels, which share neither path, to the FP32 parity tolerances."""
+    p, fl = W.rayleigh_taylor(256, nz=416)
+    n = p["nx"] * p["ny"] * p["nz"]
+    assert 20 * (-(-n // 64) * 64) * 4 >= 2 ** 31
+    a = gpu_run([(p, fl)], 20, level="compact")[0]
+    b = gpu_run([(p, fl)], 20, level="pair")[0]
+    e = {k: float(np.abs(a[k] - b[k]).max()) for k in ("rhoN", "ux", "uy", "uz", "rhoR", "rhoB")}
+    print("compact (per-pair resources) vs pair levels", e, flush=True)
+    assert np.isfinite(list(e.values())).all()
+    assert e["rhoN"] <= 1e-5 and max(e["ux"], e["uy"], e["uz"]) <= 1e-6, e
+    assert e["rhoR"] <= 1e-5 * p["rho_in"][0] and e["rhoB"] <= 1e-5 * p["rho_in"][1], e
+
+
 def test_compact_handle_with_a_reinitialised_case():
     """In a compact handle, lbcg_set_fields puts one case back to a pair-format
     start level while the other stays compact: the next step runs the two
