@@ -355,7 +355,7 @@ def test_default_chunk_fills_the_workgroup_slots():
     """The default z-chunk minimises ceil(T / S) (zc + 2) over 8 .. 128 planes
     (FP32) or 8 .. 64 (16-bit forms), the longer on a tie, with T(zc) the
     tiles of 32 x 8 columns and S the GPU's workgroup slots: CUs x workgroups
-    per CU of the kernel, as built 2 for FP32 compact levels (229 VGPRs, 76 KB
+    per CU of the kernel, as built 2 for FP32 compact levels (228 VGPRs, 76 KB
     LDS) and 3 for 16-bit pairs (167 VGPRs, 41 KB).  Boxes chosen so that
     neither bound decides (e.g. 128 x 64 x 256: 17 planes would still fill
     the slots but leave a last chunk of one plane; 16 balances)."""
