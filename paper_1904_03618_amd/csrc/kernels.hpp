@@ -257,7 +257,10 @@ constexpr int RH = 2;                    // halo of the stored-density planes ar
 constexpr int RW = FTX + 2 * RH, RREG = RW * (FTY + 2 * RH);
 
 // Issue phase: the 19 population loads of a node, all in flight at once.
-template <int ST, int CPP, int I = 0>
+// SO: the case's level (19 NS pairs) lies below 2^31 bytes and is read
+// through one buffer resource, each direction pair's arrays reached by a
+// scalar offset; otherwise each pair has a resource of its own.
+template <int ST, int CPP, bool SO = false, int I = 0>
 __device__ inline void pull_issue(const StepArgs &a, DC &C, const Coord &c, typename Storage<ST>::P (&v)[Q])
 {
     if constexpr (I < Q) {
@@ -270,8 +273,12 @@ __device__ inline void pull_issue(const StepArgs &a, DC &C, const Coord &c, type
         constexpr bool hi_own = I != F, hi_opp = opp(I) != F;
         const bool hi = bb ? hi_opp : hi_own;
         const uint32_t e = si + (hi ? (uint32_t)NS : 0u);
-        v[I] = buf_ld<P, CPP>(rsrc(base + (size_t)F * NS, W * NS * sizeof(P)), e * (uint32_t)sizeof(P));
-        pull_issue<ST, CPP, I + 1>(a, C, c, v);
+        if constexpr (SO)
+            v[I] = buf_ld_so<P, CPP>(rsrc(base, 19 * NS * sizeof(P)), e * (uint32_t)sizeof(P),
+                                     (uint32_t)(F * NS * sizeof(P)));
+        else
+            v[I] = buf_ld<P, CPP>(rsrc(base + (size_t)F * NS, W * NS * sizeof(P)), e * (uint32_t)sizeof(P));
+        pull_issue<ST, CPP, SO, I + 1>(a, C, c, v);
     }
 }
 
@@ -1030,7 +1037,7 @@ template <int ST, int IN, int CPP, bool SO = false>
 __device__ inline void fpull_issue(const StepArgs &a, DC &C, const Coord &c, FPull<ST, IN> &p)
 {
     if constexpr (IN == LV_COMPACT) pull_issue_c<ST, CPP, SO>(a, C, c, p);
-    else pull_issue<ST, CPP>(a, C, c, p.v);
+    else pull_issue<ST, CPP, SO>(a, C, c, p.v);
 }
 
 template <int ST, int IN, bool MV>
@@ -1251,8 +1258,8 @@ __device__ inline void stencil_lds(float4 (*ring)[FREG], int z, int tx, int ty, 
 // WL: WALLS_NONE or WALLS_Z (cases with walls on other axes take the two-pass step).
 // IN, OUT: level format read and written (LV_PAIR -> LV_PAIR, or -> LV_COMPACT;
 // LV_COMPACT -> LV_COMPACT).
-// SO: compact levels read through one buffer resource per case (the host
-// takes it where every case's level is below 2^31 bytes).
+// SO: levels read through one buffer resource per case (the host takes it
+// where every case's level is below 2^31 bytes).
 template <int ST, bool MV, int WL, int IN, int OUT, bool SO = false>
 __global__ __launch_bounds__(FNT) void k_fused(FusedArgs fa)
 {

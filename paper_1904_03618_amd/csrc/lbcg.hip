@@ -59,7 +59,7 @@ struct lbcg_handle {
     float4 *dsc[2] = {nullptr, nullptr};
     float *crs[2] = {nullptr, nullptr};
     std::vector<uint8_t> pairlvl;      // per case: its current level is in pair format
-    bool one_rsrc = false;             // every case's compact level fits one buffer resource (< 2^31 bytes)
+    bool one_rsrc[2] = {false, false}; // per level format: every case's level fits one buffer resource
     double *partial = nullptr, *red = nullptr;
     int64_t steps = 0, total_nodes = 0, total_pop = 0, total_ghost = 0;
     float scale = 1.0f, inv_scale = 1.0f;
@@ -274,13 +274,14 @@ void launch_fused(lbcg_handle *h, hipStream_t st, const FusedArgs &fa, int grid)
     else hipLaunchKernelGGL((k_fused<ST, false, WALLS_NONE, IN, OUT, SO>), g, b, 0, st, fa);
 }
 
-// Compact input levels of a handle whose cases all fit one buffer resource
-// take the single-resource instantiation (fewer scalar registers live).
+// A step that reads and writes one level format, with every case's level
+// within one buffer resource, takes the single-resource instantiation (fewer
+// scalar registers live); the one-off pair-to-compact conversion does not.
 template <int ST, int IN, int OUT>
 void launch_fused(lbcg_handle *h, hipStream_t st, const FusedArgs &fa, int grid)
 {
-    if constexpr (IN == LV_COMPACT) {
-        if (h->one_rsrc) {
+    if constexpr (IN == OUT) {
+        if (h->one_rsrc[IN]) {
             launch_fused<ST, IN, OUT, true>(h, st, fa, grid);
             return;
         }
@@ -306,10 +307,7 @@ int fused_blocks_per_cu(const lbcg_handle *h)
 template <int ST, int LV>
 int fused_blocks_per_cu(const lbcg_handle *h)
 {
-    if constexpr (LV == LV_COMPACT) {
-        if (h->one_rsrc) return fused_blocks_per_cu<ST, LV, true>(h);
-    }
-    return fused_blocks_per_cu<ST, LV, false>(h);
+    return h->one_rsrc[LV] ? fused_blocks_per_cu<ST, LV, true>(h) : fused_blocks_per_cu<ST, LV, false>(h);
 }
 
 int fused_blocks_per_cu(const lbcg_handle *h)
@@ -682,9 +680,13 @@ int lbcg_init(const lbcg_case *cases, int32_t n_cases, const lbcg_fields *init, 
                    ? LV_COMPACT
                    : LV_PAIR;
     h->pairlvl.assign(n_cases, 1);
-    h->one_rsrc = true;
-    for (const DevCase &d : h->dc)
-        if ((int64_t)20 * d.NS * (o.storage == LBCG_FP32 ? 4 : 2) >= ((int64_t)1 << 31)) h->one_rsrc = false;
+    // level bytes: pairs 19 NS pairs, compact levels 20 NS values
+    h->one_rsrc[LV_PAIR] = h->one_rsrc[LV_COMPACT] = true;
+    for (const DevCase &d : h->dc) {
+        const int64_t elem = o.storage == LBCG_FP32 ? 4 : 2, lim = (int64_t)1 << 31;
+        if ((int64_t)38 * d.NS * elem >= lim) h->one_rsrc[LV_PAIR] = false;
+        if ((int64_t)20 * d.NS * elem >= lim) h->one_rsrc[LV_COMPACT] = false;
+    }
     h->zc = o.zchunk;
     if (h->zc == 0 && h->fused) {
         // default chunk: a workgroup's tile of zc planes pulls zc + 2 planes,

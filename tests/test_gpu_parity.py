@@ -387,11 +387,12 @@ def test_default_chunk_fills_the_workgroup_slots():
 
 
 def test_compact_levels_beyond_one_buffer_resource():
-    """A case whose compact FP32 level reaches 2^31 bytes (a 256 x 256 x 416
-    Rayleigh-Taylor box, 27.3 M nodes) reads it through one buffer resource
-    per direction pair (smaller levels take one resource per level and
-    scalar offsets): after 20 steps it agrees with the same case on pair
-    levels, which share neither path, to the FP32 parity tolerances."""
+    """A case whose FP32 level reaches 2^31 bytes (a 256 x 256 x 416
+    Rayleigh-Taylor box, 27.3 M nodes; compact levels 2.2 GB, pair levels
+    4.1 GB) reads it through one buffer resource per direction pair (smaller
+    levels take one resource per level and scalar offsets): after 20 steps
+    the compact run agrees with the pair run, which shares neither its level
+    format nor its decode, to the FP32 parity tolerances."""
     p, fl = W.rayleigh_taylor(256, nz=416)
     n = p["nx"] * p["ny"] * p["nz"]
     assert 20 * (-(-n // 64) * 64) * 4 >= 2 ** 31
